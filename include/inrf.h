@@ -1,0 +1,246 @@
+/*
+ * inrf.h -- C ABI of an MI355X (gfx950) implementation of the i-NOLF
+ * one-query-per-ray render path (Luo et al., "NEPHELE: A Neural Platform for
+ * Highly Realistic Cloud Radiance Rendering", arXiv 2303.04086).
+ *
+ * Per ray the path finds the hit point on a triangle-mesh geometry proxy,
+ * looks up multi-level features through perfect spatial hash tables with
+ * trilinear blending (Sec. 4.1, Eq. 1), encodes the view direction with real
+ * spherical harmonics of bands 0..3, and evaluates a small MLP that gives the
+ * colour and opacity of the local opacity light field (Sec. 4.2, Eqs. 2-3).
+ *
+ * Conventions for every call:
+ *   - Status codes: INRF_OK (0) or a negative INRF_E_* value; the message of
+ *     the last failure on the calling thread is returned by inrf_last_error().
+ *   - Arguments are validated before anything is enqueued; on an error no
+ *     work is enqueued and no output is written.
+ *   - "device" pointers are HIP device memory owned by the caller; "host"
+ *     pointers are ordinary process memory owned by the caller, consumed
+ *     before the call returns.  Device calls never allocate, never free and
+ *     never synchronise: they enqueue on `stream` (a hipStream_t; NULL = the
+ *     null stream) and return; results are valid once the caller has
+ *     synchronised that stream.  Device faults surface at that point.
+ *   - No C++ exception crosses this boundary.  Calls are reentrant; calls on
+ *     different streams may run concurrently if they do not share output or
+ *     workspace memory.
+ *   - Misses (including rays with a non-finite origin or direction, or a zero
+ *     direction) are defined outputs, not errors: RGBA (0,0,0,0), t = +inf,
+ *     triangle -1.
+ */
+#ifndef INRF_H
+#define INRF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t inrf_status;
+
+#define INRF_OK 0
+#define INRF_E_INVALID (-1)     /* bad argument, shape or layout; nothing enqueued */
+#define INRF_E_SIZE (-2)        /* caller buffer or workspace too small */
+#define INRF_E_BUILD (-3)       /* a host build did not succeed within its limits */
+#define INRF_E_DEVICE (-4)      /* HIP runtime or launch error */
+#define INRF_E_UNSUPPORTED (-5) /* combination not compiled in */
+
+/* Element types of feature tables and low-precision weight copies. */
+#define INRF_F32 0
+#define INRF_F16 1
+#define INRF_BF16 2
+
+/* Arithmetic of the network evaluation. */
+#define INRF_PREC_FP32 0 /* FP32 operands, FP32 matrix cores, FP32 accumulation */
+#define INRF_PREC_FP16 1 /* FP16 operands on matrix cores, FP32 accumulation */
+#define INRF_PREC_BF16 2 /* BF16 operands on matrix cores, FP32 accumulation */
+
+#define INRF_MAX_LEVELS 32
+#define INRF_FEATURES 2  /* features per level (F) */
+#define INRF_SH_DIM 16   /* real SH bands 0..3 */
+#define INRF_HIDDEN 64   /* width of both hidden layers */
+#define INRF_OUT 4       /* R, G, B, alpha */
+
+/* Thread-local message of the last failed call ("" if none). */
+const char* inrf_last_error(void);
+/* Library version, major * 10000 + minor * 100 + patch. */
+int32_t inrf_version(void);
+
+/* ------------------------------------------------------------------------
+ * Host-side builders.  Synchronous, deterministic (independent of the
+ * thread count), touch no device memory.
+ * ---------------------------------------------------------------------- */
+
+/* Parameters of the perfect-spatial-hash build (Sec. 4.1: the offset table is
+ * precomputed from an occupancy field with a heuristic that favours mapping
+ * neighbouring points to neighbouring slots).
+ *   seed          seeds the pseudo-random candidate offsets
+ *   dilate        occupied cells = cells within this Chebyshev distance of a
+ *                 cell whose closed box meets a proxy triangle (>= 0)
+ *   load_pct      table side mbar = smallest with load_pct*mbar^3 >= 100*n
+ *                 (1..100)
+ *   bucket_keys   offset-table side rbar starts at the smallest value with
+ *                 bucket_keys*rbar^3 >= n (>= 1), then grows until
+ *                 gcd(mbar, rbar) = 1 and mbar*rbar >= N+1
+ *   n_random      pseudo-random candidate offsets tried per bucket
+ *   max_restarts  rbar increases before mbar is increased
+ *   n_threads     worker threads for voxelisation (0 = hardware count) */
+typedef struct inrf_psh_params {
+    uint64_t seed;
+    int32_t dilate;
+    int32_t load_pct;
+    int32_t bucket_keys;
+    int32_t n_random;
+    int32_t max_restarts;
+    int32_t n_threads;
+} inrf_psh_params;
+
+/* Fills the defaults: seed 1, dilate 1, load_pct 80, bucket_keys 2,
+ * n_random 32, max_restarts 4, n_threads 0. */
+void inrf_psh_params_default(inrf_psh_params* p);
+
+typedef struct inrf_psh inrf_psh; /* opaque host object */
+
+typedef struct inrf_psh_level_info {
+    int32_t res;      /* grid resolution N (cells per axis; vertices 0..N) */
+    int32_t mbar;     /* hash table side: mbar^3 slots */
+    int32_t rbar;     /* offset table side: rbar^3 entries */
+    int32_t restarts; /* rebuilds needed (rbar or mbar increases) */
+    int64_t n_keys;   /* occupied vertices */
+    int64_t n_slots;  /* mbar^3 */
+    int64_t n_phi;    /* rbar^3 */
+} inrf_psh_level_info;
+
+/* Voxelise the proxy at each resolution res[l] (occupied vertices of Sec. 4.2,
+ * "Implementation with PSH encoding"), then build each level's offset table
+ * Phi and key->slot map (Sec. 4.1, Eq. 1):
+ *     slot(p) = (p + Phi[p mod rbar]) mod mbar   (component-wise),
+ *     linear slot = (s_z*mbar + s_y)*mbar + s_x.
+ * verts: host float32 [n_verts][3], every coordinate in [0,1] and a multiple
+ * of 2^-16 (so occupancy is decided exactly in integers); tris: host int32
+ * [n_tris][3] vertex indices.  res: host int32 [n_levels], each in
+ * [1, 4096].  On success *out owns the result (free with inrf_psh_free).
+ * Errors: INRF_E_INVALID (bad sizes, vertex off the 2^-16 lattice or outside
+ * [0,1], index out of range), INRF_E_BUILD (mbar would exceed 1024). */
+inrf_status inrf_build_psh(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                           int32_t n_levels, const int32_t* res, const inrf_psh_params* params,
+                           inrf_psh** out);
+
+/* Build one level from a caller-supplied occupied vertex set (for occupancy
+ * that does not come from a mesh, e.g. shape from silhouette).
+ * keys: host int64 [n_keys] linear vertex keys (z*(N+1)+y)*(N+1)+x, strictly
+ * ascending.  params->dilate is ignored. */
+inrf_status inrf_build_psh_keys(int32_t res, const int64_t* keys, int64_t n_keys,
+                                const inrf_psh_params* params, inrf_psh** out);
+
+/* Number of levels of a built object. */
+int32_t inrf_psh_levels(const inrf_psh* psh);
+
+/* Copy one level out.  info is required; keys (int64 [n_keys], canonical
+ * ascending linear keys), phi (uint32 [n_phi], packed x | y<<10 | z<<20) and
+ * slots (int32 [n_keys], linear slot of each key in key order) are optional
+ * host buffers of the sizes given by info. */
+inrf_status inrf_psh_level(const inrf_psh* psh, int32_t level, inrf_psh_level_info* info,
+                           int64_t* keys, uint32_t* phi, int32_t* slots);
+
+void inrf_psh_free(inrf_psh* psh);
+
+typedef struct inrf_bvh inrf_bvh; /* opaque host object */
+
+typedef struct inrf_bvh_info {
+    int64_t n_nodes;    /* binary nodes */
+    int64_t node_bytes; /* size of the node image */
+    int64_t tri_bytes;  /* size of the triangle image */
+    int32_t depth;      /* deepest leaf (root = 1), at most 32 */
+    int32_t max_leaf;   /* triangles per leaf, at most 4 */
+} inrf_bvh_info;
+
+/* Binned-SAH bounding volume hierarchy over the proxy (the paper queries a
+ * geometry proxy per ray, abstract and Sec. 1; this is its acceleration
+ * structure).  Same vertex/triangle arguments as inrf_build_psh, except that
+ * coordinates need not lie on the lattice (they must be finite). */
+inrf_status inrf_build_bvh(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                           inrf_bvh** out);
+inrf_status inrf_bvh_get_info(const inrf_bvh* bvh, inrf_bvh_info* info);
+/* Copy the node and triangle images (opaque layouts) into host buffers of
+ * info.node_bytes and info.tri_bytes; the caller uploads them to the device
+ * and points inrf_model at them. */
+inrf_status inrf_bvh_copy(const inrf_bvh* bvh, void* nodes, void* tri_data);
+void inrf_bvh_free(inrf_bvh* bvh);
+
+/* ------------------------------------------------------------------------
+ * Device model: a plain view of caller-owned device memory.
+ * ---------------------------------------------------------------------- */
+
+typedef struct inrf_level_desc {
+    int32_t res, mbar, rbar, pad;
+    int64_t phi_offset;  /* first entry of this level in `phi` */
+    int64_t slot_offset; /* first slot of this level in `table` */
+} inrf_level_desc;
+
+typedef struct inrf_model {
+    int32_t n_levels;    /* L, 1..INRF_MAX_LEVELS */
+    int32_t table_dtype; /* INRF_F32 or INRF_F16 */
+    inrf_level_desc levels[INRF_MAX_LEVELS];
+    const uint32_t* phi;    /* device, packed offsets of all levels */
+    const void* table;      /* device, [total slots][INRF_FEATURES] of table_dtype;
+                               slots of unoccupied vertices hold zeros */
+    const float* weights;   /* device FP32 W1 [64][d_in] | W2 [64][64] | W3 [4][64],
+                               row-major [out][in], d_in = 2*L + 16; the FP16 and
+                               BF16 precisions round them on the fly */
+    const void* bvh_nodes;  /* device image from inrf_bvh_copy */
+    const void* bvh_tris;   /* device image from inrf_bvh_copy */
+    int64_t n_tris;         /* proxy triangles; 0 = empty proxy (every ray misses) */
+} inrf_model;
+
+/* Pinhole camera (pose and intrinsics as a client sends them).  Pixel (i
+ * from the top, j from the left) of a width x height image has ray index
+ * i*width + j, origin `origin` and direction
+ *     normalize(forward + s_x*right + s_y*up),
+ *     s_x = (2(j+1/2)/width - 1) * tan_half_fov_y * width/height,
+ *     s_y = (1 - 2(i+1/2)/height) * tan_half_fov_y. */
+typedef struct inrf_camera {
+    float origin[3], right[3], up[3], forward[3];
+    float tan_half_fov_y;
+    int32_t width, height;
+} inrf_camera;
+
+/* Workspace bytes needed by inrf_render / inrf_forward for up to n_rays rays. */
+int64_t inrf_workspace_size(int64_t n_rays);
+
+/* Render one camera: rgba (device float32 [height*width][4], row-major, top
+ * row first, not premultiplied), and optionally depth (device float32
+ * [height*width], distance along the unit ray, +inf on a miss) and tri
+ * (device int32 [height*width], proxy triangle index, -1 on a miss).
+ * ws: device workspace of at least inrf_workspace_size(width*height) bytes. */
+inrf_status inrf_render(const inrf_model* m, int32_t precision, const inrf_camera* cam, float* rgba,
+                        float* depth, int32_t* tri, void* ws, int64_t ws_bytes, void* stream);
+
+/* The same path on a batch of rays ("an indiscriminate range of rays with
+ * depths", Sec. 1): ray_o, ray_d device float32 [n][3] (d need not be unit;
+ * depth is then the ray parameter t); rgba device float32 [n][4]; depth and
+ * tri optional as in inrf_render. */
+inrf_status inrf_forward(const inrf_model* m, int32_t precision, const float* ray_o, const float* ray_d,
+                         int64_t n, float* rgba, float* depth, int32_t* tri, void* ws, int64_t ws_bytes,
+                         void* stream);
+
+/* Closest hit only: tri (device int32 [n]) and t (device float32 [n]). */
+inrf_status inrf_trace(const inrf_model* m, const float* ray_o, const float* ray_d, int64_t n, int32_t* tri,
+                       float* t, void* stream);
+
+/* Position encoding E(x) (Sec. 4.1): x device float32 [n][3] (clamped to
+ * [0,1]); enc device float32 [n][2L], level 0 first; slots optional device
+ * int32 [n][L][8] (level-local linear slot of corner c = cx + 2cy + 4cz). */
+inrf_status inrf_encode(const inrf_model* m, const float* x, int64_t n, float* enc, int32_t* slots,
+                        void* stream);
+
+/* The network alone (Sec. 4.2, Eq. 3): in device float32 [n][d_in] (encoding
+ * then 16 SH values), rgba device float32 [n][4]. */
+inrf_status inrf_mlp(const inrf_model* m, int32_t precision, const float* in, int64_t n, float* rgba,
+                     void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* INRF_H */

@@ -1,0 +1,156 @@
+// Device-side building blocks shared by the kernels of libinrf: model view,
+// exact grid cell, perfect-spatial-hash lookup with trilinear blend, real
+// spherical harmonics.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include "bvh_layout.hpp"
+#include "inrf.h"
+
+namespace inrf {
+namespace dev {
+
+struct LevelC {
+    int32_t res, mbar, rbar, pad;
+    float inv_mbar, inv_rbar;
+    int64_t phi_off, slot_off;
+};
+
+struct ModelC {
+    int32_t n_levels, table_dtype;
+    const uint32_t* phi;
+    const void* table;
+    const float* weights;
+    const BvhNode* nodes;
+    const BvhTri* tris;
+    int64_t n_tris;
+    LevelC lv[INRF_MAX_LEVELS];
+};
+
+// a mod m for 0 <= a < 2^14, 1 <= m <= 2^14, via a float reciprocal and one
+// correction step (the quotient estimate is off by at most one).
+__device__ __forceinline__ int mod_small(int a, int m, float inv_m) {
+    const int d = int(float(a) * inv_m);
+    int r = a - d * m;
+    if (r < 0) r += m;
+    else if (r >= m) r -= m;
+    return r;
+}
+
+// Cell of x (already in [0,1]) on a grid of N cells: p = floor of the exact
+// product N*x, clamped to N-1, and w = N*x - p rounded once (Sec. 4.1: scale
+// by the resolution, take the floor).  fl(N*x) can round up onto an integer
+// while the exact product lies below it; the FMA residual detects that.
+__device__ __forceinline__ void cell_of(float x, int N, int& p, float& w) {
+    const float fn = float(N);
+    const float y = fn * x;
+    const float e = __builtin_fmaf(fn, x, -y);  // exact: N*x - fl(N*x)
+    float fl = floorf(y);
+    if (fl == y && e < 0.f) fl -= 1.f;
+    fl = fminf(fl, fn - 1.f);
+    p = int(fl);
+    w = __builtin_fmaf(fn, x, -fl);
+}
+
+__device__ __forceinline__ float clamp01(float v) { return fminf(fmaxf(v, 0.f), 1.f); }
+
+template <class T>
+struct TableRead;
+template <>
+struct TableRead<float> {
+    __device__ static float2 get(const void* t, int64_t i) { return reinterpret_cast<const float2*>(t)[i]; }
+};
+template <>
+struct TableRead<__half> {
+    __device__ static float2 get(const void* t, int64_t i) {
+        return __half22float2(reinterpret_cast<const __half2*>(t)[i]);
+    }
+};
+
+// Perfect-spatial-hash encoding of one level (Sec. 4.1, Eq. 1):
+//   slot(v) = (v mod mbar + Phi[v mod rbar]) mod mbar, component-wise,
+// for the eight corners v = p + c of x's cell, blended trilinearly with
+// corner c = cx + 2cy + 4cz weighted prod_i (c_i ? w_i : 1 - w_i), summed in
+// ascending c.  Optionally reports the eight level-local linear slots.
+template <class T>
+__device__ __forceinline__ float2 encode_level(const ModelC& m, const LevelC& L, float x, float y, float z,
+                                               int* slots_out) {
+    int px, py, pz;
+    float wx, wy, wz;
+    cell_of(x, L.res, px, wx);
+    cell_of(y, L.res, py, wy);
+    cell_of(z, L.res, pz, wz);
+    const int qx = mod_small(px, L.rbar, L.inv_rbar), qy = mod_small(py, L.rbar, L.inv_rbar),
+              qz = mod_small(pz, L.rbar, L.inv_rbar);
+    const int hx = mod_small(px, L.mbar, L.inv_mbar), hy = mod_small(py, L.mbar, L.inv_mbar),
+              hz = mod_small(pz, L.mbar, L.inv_mbar);
+    const int qx1 = (qx + 1 == L.rbar) ? 0 : qx + 1, qy1 = (qy + 1 == L.rbar) ? 0 : qy + 1,
+              qz1 = (qz + 1 == L.rbar) ? 0 : qz + 1;
+    const uint32_t* phi = m.phi + L.phi_off;
+    uint32_t o[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int cx = (c & 1) ? qx1 : qx, cy = (c & 2) ? qy1 : qy, cz = (c & 4) ? qz1 : qz;
+        o[c] = phi[(cz * L.rbar + cy) * L.rbar + cx];
+    }
+    float2 f[8];
+    int sl[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        int sx = hx + ((c & 1) ? 1 : 0), sy = hy + ((c & 2) ? 1 : 0), sz = hz + ((c & 4) ? 1 : 0);
+        sx += int(o[c] & 1023u);
+        sy += int((o[c] >> 10) & 1023u);
+        sz += int((o[c] >> 20) & 1023u);
+        // (p + c) mod mbar <= mbar and an offset < mbar: one subtraction
+        // reduces the sum; the second step keeps a corrupt offset in bounds
+        if (sx >= L.mbar) sx -= L.mbar;
+        if (sy >= L.mbar) sy -= L.mbar;
+        if (sz >= L.mbar) sz -= L.mbar;
+        if (sx >= L.mbar) sx = mod_small(sx, L.mbar, L.inv_mbar);
+        if (sy >= L.mbar) sy = mod_small(sy, L.mbar, L.inv_mbar);
+        if (sz >= L.mbar) sz = mod_small(sz, L.mbar, L.inv_mbar);
+        sl[c] = (sz * L.mbar + sy) * L.mbar + sx;
+        f[c] = TableRead<T>::get(m.table, L.slot_off + sl[c]);
+    }
+    if (slots_out) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) slots_out[c] = sl[c];
+    }
+    const float ux = 1.f - wx, uy = 1.f - wy, uz = 1.f - wz;
+    float2 e = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const float wc = ((c & 1) ? wx : ux) * ((c & 2) ? wy : uy) * ((c & 4) ? wz : uz);
+        e.x += wc * f[c].x;
+        e.y += wc * f[c].y;
+    }
+    return e;
+}
+
+// Real spherical harmonics of bands 0..3 of a unit vector, index l*l + l + m,
+// orthonormal, Condon-Shortley phase (closed-form polynomials).
+__device__ __forceinline__ void sh16(float x, float y, float z, float* o) {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    o[0] = 0.28209479177387814f;
+    o[1] = -0.48860251190291992f * y;
+    o[2] = 0.48860251190291992f * z;
+    o[3] = -0.48860251190291992f * x;
+    o[4] = 1.0925484305920792f * x * y;
+    o[5] = -1.0925484305920792f * y * z;
+    o[6] = 0.31539156525252005f * (3.f * zz - 1.f);
+    o[7] = -1.0925484305920792f * x * z;
+    o[8] = 0.54627421529603959f * (xx - yy);
+    o[9] = -0.59004358992664352f * y * (3.f * xx - yy);
+    o[10] = 2.8906114426405538f * x * y * z;
+    o[11] = -0.45704579946446572f * y * (5.f * zz - 1.f);
+    o[12] = 0.3731763325901154f * z * (5.f * zz - 3.f);
+    o[13] = -0.45704579946446572f * x * (5.f * zz - 1.f);
+    o[14] = 1.4453057213202769f * z * (xx - yy);
+    o[15] = -0.59004358992664352f * x * (xx - 3.f * yy);
+}
+
+}  // namespace dev
+}  // namespace inrf

@@ -1,0 +1,698 @@
+// Device entry points of libinrf: closest-hit trace, position encoding, the
+// network alone, and the fused per-ray path (inrf_render / inrf_forward).
+//
+// A frame is three launches on the caller's stream:
+//   k_reset  clears the hit counter in the workspace;
+//   k_trace  one ray per lane: generate (camera) or load (batch) the ray,
+//            closest hit through the BVH with a watertight triangle test,
+//            write depth / triangle / zero colour for misses, and append the
+//            hit record (hit point, unit direction, output index) to a packed
+//            list, one atomic per wave;
+//   k_shade  persistent waves over the packed hits: multi-level PSH gather with
+//            trilinear blend, SH16 of the direction, the MLP on matrix cores,
+//            sigmoid, colour write.
+// Each ray's colour depends only on that ray, so results do not depend on the
+// order in which waves append hits.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "bvh_layout.hpp"
+#include "device_common.hpp"
+#include "host_common.hpp"
+#include "inrf.h"
+#include "mlp_device.hpp"
+
+namespace inrf {
+namespace dev {
+
+constexpr int kTile = 16;      // camera tiles of 16x16 pixels
+constexpr int kThreads = 256;  // 4 waves
+
+struct alignas(16) HitRec {
+    float x, y, z;
+    int32_t out;  // output (pixel) index
+    float dx, dy, dz;
+    int32_t pad;
+};
+
+struct CamC {
+    float o[3], r[3], u[3], f[3];
+    float tan_y, tan_x;  // tan(fov_y/2) and tan(fov_y/2)*W/H
+    int32_t W, H, tiles_x;
+};
+
+struct TraceArgs {
+    const float* ray_o;  // batch mode
+    const float* ray_d;
+    int64_t n;
+    float* rgba;    // nullable
+    float* depth;   // nullable
+    int32_t* tri;   // nullable
+    HitRec* recs;   // nullable: no records (trace only)
+    int32_t* counter;
+};
+
+// ------------------------------------------------------------- tracing ----
+
+__device__ __forceinline__ float comp(const float3& v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
+
+struct RayPre {
+    float3 o, d, inv;
+    int kx, ky, kz;
+    float Sx, Sy, Sz;
+};
+
+__device__ __forceinline__ RayPre ray_setup(float3 o, float3 d) {
+    RayPre R;
+    R.o = o;
+    R.d = d;
+    R.inv = make_float3(1.f / d.x, 1.f / d.y, 1.f / d.z);
+    const float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
+    int kz = 0;
+    if (ay > ax) kz = 1;
+    if (az > fmaxf(ax, ay)) kz = 2;
+    int kx = kz + 1 == 3 ? 0 : kz + 1;
+    int ky = kx + 1 == 3 ? 0 : kx + 1;
+    if (comp(d, kz) < 0.f) {
+        const int t = kx;
+        kx = ky;
+        ky = t;
+    }
+    R.kx = kx;
+    R.ky = ky;
+    R.kz = kz;
+    const float dz = comp(d, kz);
+    R.Sx = comp(d, kx) / dz;
+    R.Sy = comp(d, ky) / dz;
+    R.Sz = 1.f / dz;
+    return R;
+}
+
+// Watertight ray/triangle test of Woop, Benthin and Wald (JCGT 2013),
+// two-sided.  Returns t > 0 of the hit or +inf.  Products are not fused so
+// that an edge shared by two triangles gets exactly opposite edge values.
+__device__ __forceinline__ float hit_triangle(const RayPre& R, const float3 v0, const float3 v1, const float3 v2) {
+#pragma clang fp contract(off)
+    const float3 A = make_float3(v0.x - R.o.x, v0.y - R.o.y, v0.z - R.o.z);
+    const float3 B = make_float3(v1.x - R.o.x, v1.y - R.o.y, v1.z - R.o.z);
+    const float3 C = make_float3(v2.x - R.o.x, v2.y - R.o.y, v2.z - R.o.z);
+    const float Akz = comp(A, R.kz), Bkz = comp(B, R.kz), Ckz = comp(C, R.kz);
+    const float Ax = comp(A, R.kx) - R.Sx * Akz, Ay = comp(A, R.ky) - R.Sy * Akz;
+    const float Bx = comp(B, R.kx) - R.Sx * Bkz, By = comp(B, R.ky) - R.Sy * Bkz;
+    const float Cx = comp(C, R.kx) - R.Sx * Ckz, Cy = comp(C, R.ky) - R.Sy * Ckz;
+    float U = Cx * By - Cy * Bx;
+    float V = Ax * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax;
+    if (U == 0.f || V == 0.f || W == 0.f) {
+        U = float(double(Cx) * double(By) - double(Cy) * double(Bx));
+        V = float(double(Ax) * double(Cy) - double(Ay) * double(Cx));
+        W = float(double(Bx) * double(Ay) - double(By) * double(Ax));
+    }
+    if ((U < 0.f || V < 0.f || W < 0.f) && (U > 0.f || V > 0.f || W > 0.f)) return INFINITY;
+    float det = U + V + W;
+    if (det == 0.f) return INFINITY;
+    const float Az = R.Sz * Akz, Bz = R.Sz * Bkz, Cz = R.Sz * Ckz;
+    float T = U * Az + V * Bz + W * Cz;
+    if (det < 0.f) {
+        T = -T;
+        det = -det;
+    }
+    if (!(T > 0.f)) return INFINITY;
+    return T / det;
+}
+
+// Slab test against [lo, hi] for t in [0, tmax]; conservative by 2*gamma(3)
+// (Ize 2013) so that rounding never rejects a box a ray touches.
+__device__ __forceinline__ bool hit_box(const RayPre& R, const float* lo, const float* hi, float tmax, float& tnear) {
+    const float t0x = (lo[0] - R.o.x) * R.inv.x, t1x = (hi[0] - R.o.x) * R.inv.x;
+    const float t0y = (lo[1] - R.o.y) * R.inv.y, t1y = (hi[1] - R.o.y) * R.inv.y;
+    const float t0z = (lo[2] - R.o.z) * R.inv.z, t1z = (hi[2] - R.o.z) * R.inv.z;
+    const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.f));
+    const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
+    tnear = tn;
+    return tn <= tf * 1.00000024f;
+}
+
+__device__ __forceinline__ void leaf(const RayPre& R, const BvhTri* __restrict__ tris, int32_t ref, float& best_t,
+                                     int32_t& best_i) {
+    const int32_t code = ~ref;
+    const int32_t first = code >> 3, count = code & 7;
+    for (int32_t k = 0; k < count; ++k) {
+        const float4* p = reinterpret_cast<const float4*>(tris + first + k);
+        const float4 a = p[0], b = p[1], c = p[2];
+        const float t = hit_triangle(R, make_float3(a.x, a.y, a.z), make_float3(b.x, b.y, b.z),
+                                     make_float3(c.x, c.y, c.z));
+        const int32_t idx = __float_as_int(a.w);
+        if (t < best_t || (t == best_t && t != INFINITY && idx < best_i)) {
+            best_t = t;
+            best_i = idx;
+        }
+    }
+}
+
+// Closest hit through the BVH; `stack` is this lane's column of an LDS stack
+// with stride kThreads (depth <= 32 guarantees at most 31 pushes).
+__device__ void closest_hit(const ModelC& m, const RayPre& R, int* stack, float& best_t, int32_t& best_i) {
+    best_t = INFINITY;
+    best_i = -1;
+    if (m.n_tris == 0) return;
+    int node = 0, sp = 0;
+    // a valid image visits each node at most once; the cap only guarantees
+    // termination for a corrupt one
+    for (int visits = 0; visits < (1 << 20); ++visits) {
+        const float4* p = reinterpret_cast<const float4*>(m.nodes + node);
+        const float4 q0 = p[0], q1 = p[1], q2 = p[2], q3 = p[3];
+        const float lmin[3] = {q0.x, q0.y, q0.z}, lmax[3] = {q0.w, q1.x, q1.y};
+        const float rmin[3] = {q1.z, q1.w, q2.x}, rmax[3] = {q2.y, q2.z, q2.w};
+        const int32_t left = __float_as_int(q3.x), right = __float_as_int(q3.y);
+        float tl, tr;
+        bool hl = hit_box(R, lmin, lmax, best_t, tl);
+        bool hr = hit_box(R, rmin, rmax, best_t, tr);
+        if (hl && left < 0) {
+            leaf(R, m.tris, left, best_t, best_i);
+            hl = false;
+        }
+        if (hr && right < 0) {
+            leaf(R, m.tris, right, best_t, best_i);
+            hr = false;
+        }
+        if (hl && hr && sp < kBvhMaxDepth) {
+            const bool lfirst = tl <= tr;
+            stack[(sp++) * kThreads] = lfirst ? right : left;
+            node = lfirst ? left : right;
+        } else if (hl) {
+            node = left;
+        } else if (hr) {
+            node = right;
+        } else {
+            if (sp == 0) break;
+            node = stack[(--sp) * kThreads];
+        }
+    }
+}
+
+template <bool CAMERA>
+__global__ __launch_bounds__(kThreads) void k_trace(ModelC m, CamC cam, TraceArgs a) {
+    __shared__ int stack[32 * kThreads];
+    int64_t ray;
+    bool valid;
+    float3 o, d;
+    if (CAMERA) {
+        const int tile = blockIdx.x, tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+        const int row = ty * kTile + int(threadIdx.x) / kTile, col = tx * kTile + int(threadIdx.x) % kTile;
+        valid = row < cam.H && col < cam.W;
+        ray = int64_t(row) * cam.W + col;
+        const float sx = ((2.f * (float(col) + 0.5f)) / float(cam.W) - 1.f) * cam.tan_x;
+        const float sy = (1.f - (2.f * (float(row) + 0.5f)) / float(cam.H)) * cam.tan_y;
+        float3 v = make_float3(cam.f[0] + sx * cam.r[0] + sy * cam.u[0], cam.f[1] + sx * cam.r[1] + sy * cam.u[1],
+                               cam.f[2] + sx * cam.r[2] + sy * cam.u[2]);
+        const float inv = 1.f / sqrtf(v.x * v.x + v.y * v.y + v.z * v.z);
+        d = make_float3(v.x * inv, v.y * inv, v.z * inv);
+        o = make_float3(cam.o[0], cam.o[1], cam.o[2]);
+    } else {
+        ray = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+        valid = ray < a.n;
+        if (valid) {
+            o = make_float3(a.ray_o[3 * ray], a.ray_o[3 * ray + 1], a.ray_o[3 * ray + 2]);
+            d = make_float3(a.ray_d[3 * ray], a.ray_d[3 * ray + 1], a.ray_d[3 * ray + 2]);
+        } else {
+            o = d = make_float3(0.f, 0.f, 1.f);
+        }
+    }
+    const bool finite = isfinite(o.x) && isfinite(o.y) && isfinite(o.z) && isfinite(d.x) && isfinite(d.y) &&
+                        isfinite(d.z) && (d.x != 0.f || d.y != 0.f || d.z != 0.f);
+    float t = INFINITY;
+    int32_t tri = -1;
+    if (valid && finite) {
+        const RayPre R = ray_setup(o, d);
+        closest_hit(m, R, stack + threadIdx.x, t, tri);
+    }
+    const bool hit = valid && tri >= 0;
+    if (valid) {
+        if (a.depth) a.depth[ray] = t;
+        if (a.tri) a.tri[ray] = tri;
+        if (a.rgba && !hit) reinterpret_cast<float4*>(a.rgba)[ray] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    if (a.recs) {
+        const uint64_t mask = __ballot(hit);
+        const int lane = __lane_id();
+        int base = 0;
+        if (lane == 0 && mask) base = atomicAdd(a.counter, __popcll(mask));
+        base = __shfl(base, 0);
+        if (hit) {
+            const int pos = base + __popcll(mask & ((uint64_t(1) << lane) - 1));
+            const float inv = 1.f / sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
+            HitRec h;
+            h.x = clamp01(o.x + t * d.x);
+            h.y = clamp01(o.y + t * d.y);
+            h.z = clamp01(o.z + t * d.z);
+            h.out = int32_t(ray);
+            h.dx = d.x * inv;
+            h.dy = d.y * inv;
+            h.dz = d.z * inv;
+            h.pad = 0;
+            a.recs[pos] = h;
+        }
+    }
+}
+
+__global__ void k_reset(int32_t* counter) {
+    if (threadIdx.x == 0) *counter = 0;
+}
+
+// ------------------------------------------------------------- shading ----
+
+// FP32 network: one ray per lane, first layer streamed per level.
+template <class TableT>
+__global__ __launch_bounds__(kThreads) void k_shade_f32(ModelC m, const HitRec* __restrict__ recs,
+                                                        const int32_t* __restrict__ counter, float* __restrict__ rgba) {
+    extern __shared__ float lds_f[];
+    const int d_in = 2 * m.n_levels + INRF_SH_DIM;
+    f32_stage_weights(m.weights, d_in, lds_f);
+    __syncthreads();
+    const float* L1 = lds_f;
+    const float* L2 = L1 + d_in * 64;
+    const float* L3 = L2 + 64 * 64;
+    const int n = *counter;
+    const int wave = int(threadIdx.x) / 64, lane = __lane_id();
+    for (int64_t base = (int64_t(blockIdx.x) * 4 + wave) * 64; base < n; base += int64_t(gridDim.x) * 256) {
+        const int64_t i = base + lane;
+        const bool act = i < n;
+        HitRec h;
+        if (act) h = recs[i];
+        else h = HitRec{0.5f, 0.5f, 0.5f, 0, 0.f, 0.f, 1.f, 0};
+        F32Acc a;
+        f32_zero(a);
+        for (int l = 0; l < m.n_levels; ++l) {
+            float2 e = make_float2(0.f, 0.f);
+            if (act) e = encode_level<TableT>(m, m.lv[l], h.x, h.y, h.z, nullptr);
+            f32_layer1_input(a, L1, 2 * l, e.x);
+            f32_layer1_input(a, L1, 2 * l + 1, e.y);
+        }
+        float sh[16];
+        sh16(h.dx, h.dy, h.dz, sh);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            f32_layer1_input(a, L1, 2 * m.n_levels + k, sh[k]);
+            __builtin_amdgcn_sched_barrier(0);  // keep weight loads next to their use
+        }
+        const f32x4 o = f32_tail(a, L2, L3);
+        if (act)
+            reinterpret_cast<float4*>(rgba)[h.out] =
+                make_float4(sigmoidf(o[0]), sigmoidf(o[1]), sigmoidf(o[2]), sigmoidf(o[3]));
+    }
+}
+
+// FP16/BF16 network: one ray per lane for the gather, inputs staged in LDS
+// in T, then four 16-ray blocks on 16x16x32 matrix cores.
+template <class TableT, class T, int C>
+__global__ __launch_bounds__(kThreads) void k_shade_lp(ModelC m, const HitRec* __restrict__ recs,
+                                                       const int32_t* __restrict__ counter, float* __restrict__ rgba) {
+    typedef typename LP<T>::vec V;
+    extern __shared__ float4 lds_v[];
+    const int d_in = 2 * m.n_levels + INRF_SH_DIM;
+    V* W = reinterpret_cast<V*>(lds_v);
+    lp_stage_weights<T>(m.weights, d_in, W);
+    constexpr int stride = 32 * C + 8;  // elements per LDS row
+    T* X = reinterpret_cast<T*>(W + lp_lds_vecs(d_in));
+    const int wave = int(threadIdx.x) / 64, lane = __lane_id();
+    T* Xw = X + wave * 64 * stride;
+    for (int k = 2 * m.n_levels + INRF_SH_DIM; k < 32 * C; ++k) Xw[lane * stride + k] = LP<T>::cvt(0.f);
+    __syncthreads();
+    const int n = *counter;
+    for (int64_t base = (int64_t(blockIdx.x) * 4 + wave) * 64; base < n; base += int64_t(gridDim.x) * 256) {
+        const int64_t i = base + lane;
+        const bool act = i < n;
+        HitRec h;
+        if (act) h = recs[i];
+        else h = HitRec{0.5f, 0.5f, 0.5f, 0, 0.f, 0.f, 1.f, 0};
+        T* row = Xw + lane * stride;
+        for (int l = 0; l < m.n_levels; ++l) {
+            float2 e = make_float2(0.f, 0.f);
+            if (act) e = encode_level<TableT>(m, m.lv[l], h.x, h.y, h.z, nullptr);
+            row[2 * l] = LP<T>::cvt(e.x);
+            row[2 * l + 1] = LP<T>::cvt(e.y);
+        }
+        float sh[16];
+        sh16(h.dx, h.dy, h.dz, sh);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) row[2 * m.n_levels + k] = LP<T>::cvt(sh[k]);
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        const int64_t nb = (n - base + 15) / 16;
+        for (int b = 0; b < 4 && b < nb; ++b) {
+            const f32x4 o = lp_block<T, C>(W, Xw + b * 16 * stride, stride);
+            const int src = b * 16 + (lane & 15);
+            const int out = __shfl(h.out, src);
+            if (lane < 16 && base + src < n)
+                reinterpret_cast<float4*>(rgba)[out] =
+                    make_float4(sigmoidf(o[0]), sigmoidf(o[1]), sigmoidf(o[2]), sigmoidf(o[3]));
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// --------------------------------------------------- encoder and network --
+
+template <class TableT>
+__global__ __launch_bounds__(kThreads) void k_encode(ModelC m, const float* __restrict__ x, int64_t n,
+                                                     float* __restrict__ enc, int32_t* __restrict__ slots) {
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const float px = clamp01(x[3 * i]), py = clamp01(x[3 * i + 1]), pz = clamp01(x[3 * i + 2]);
+    for (int l = 0; l < m.n_levels; ++l) {
+        int sl[8];
+        const float2 e = encode_level<TableT>(m, m.lv[l], px, py, pz, slots ? sl : nullptr);
+        enc[i * 2 * m.n_levels + 2 * l] = e.x;
+        enc[i * 2 * m.n_levels + 2 * l + 1] = e.y;
+        if (slots)
+            for (int c = 0; c < 8; ++c) slots[(i * m.n_levels + l) * 8 + c] = sl[c];
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_mlp_f32(ModelC m, const float* __restrict__ in, int64_t n,
+                                                      float* __restrict__ rgba) {
+    extern __shared__ float lds_f[];
+    const int d_in = 2 * m.n_levels + INRF_SH_DIM;
+    f32_stage_weights(m.weights, d_in, lds_f);
+    __syncthreads();
+    const float* L1 = lds_f;
+    const float* L2 = L1 + d_in * 64;
+    const float* L3 = L2 + 64 * 64;
+    const int wave = int(threadIdx.x) / 64, lane = __lane_id();
+    for (int64_t base = (int64_t(blockIdx.x) * 4 + wave) * 64; base < n; base += int64_t(gridDim.x) * 256) {
+        const int64_t i = base + lane;
+        const bool act = i < n;
+        F32Acc a;
+        f32_zero(a);
+        for (int k = 0; k < d_in; ++k) f32_layer1_input(a, L1, k, act ? in[i * d_in + k] : 0.f);
+        const f32x4 o = f32_tail(a, L2, L3);
+        if (act)
+            reinterpret_cast<float4*>(rgba)[i] =
+                make_float4(sigmoidf(o[0]), sigmoidf(o[1]), sigmoidf(o[2]), sigmoidf(o[3]));
+    }
+}
+
+template <class T, int C>
+__global__ __launch_bounds__(kThreads) void k_mlp_lp(ModelC m, const float* __restrict__ in, int64_t n,
+                                                     float* __restrict__ rgba) {
+    typedef typename LP<T>::vec V;
+    extern __shared__ float4 lds_v[];
+    const int d_in = 2 * m.n_levels + INRF_SH_DIM;
+    V* W = reinterpret_cast<V*>(lds_v);
+    lp_stage_weights<T>(m.weights, d_in, W);
+    constexpr int stride = 32 * C + 8;
+    T* X = reinterpret_cast<T*>(W + lp_lds_vecs(d_in));
+    const int wave = int(threadIdx.x) / 64, lane = __lane_id();
+    T* Xw = X + wave * 64 * stride;
+    __syncthreads();
+    for (int64_t base = (int64_t(blockIdx.x) * 4 + wave) * 64; base < n; base += int64_t(gridDim.x) * 256) {
+        // stage 64 rows (coalesced: consecutive lanes take consecutive elements)
+        for (int e = lane; e < 64 * 32 * C; e += 64) {
+            const int r = e / (32 * C), k = e % (32 * C);
+            const int64_t i = base + r;
+            Xw[r * stride + k] = LP<T>::cvt((i < n && k < d_in) ? in[i * d_in + k] : 0.f);
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        const int64_t nb = (n - base + 15) / 16;
+        for (int b = 0; b < 4 && b < nb; ++b) {
+            const f32x4 o = lp_block<T, C>(W, Xw + b * 16 * stride, stride);
+            const int64_t i = base + b * 16 + lane;
+            if (lane < 16 && i < n)
+                reinterpret_cast<float4*>(rgba)[i] =
+                    make_float4(sigmoidf(o[0]), sigmoidf(o[1]), sigmoidf(o[2]), sigmoidf(o[3]));
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+}  // namespace dev
+
+// ------------------------------------------------------------ host side ---
+namespace {
+
+using namespace dev;
+
+constexpr int64_t kWsHeader = 256;
+
+void check_hip(hipError_t e, const char* what) {
+    if (e != hipSuccess) fail(INRF_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int g_num_cus = 0;
+
+int num_cus() {
+    if (g_num_cus == 0) {
+        int dev = 0, n = 0;
+        check_hip(hipGetDevice(&dev), "hipGetDevice");
+        check_hip(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
+        g_num_cus = n > 0 ? n : 1;
+    }
+    return g_num_cus;
+}
+
+ModelC make_model(const inrf_model* m, bool need_table, bool need_bvh) {
+    require(m != nullptr, "model is NULL");
+    require(m->n_levels >= 1 && m->n_levels <= INRF_MAX_LEVELS, "n_levels must be in [1, 32]");
+    require(m->table_dtype == INRF_F32 || m->table_dtype == INRF_F16, "table_dtype must be INRF_F32 or INRF_F16");
+    ModelC c;
+    std::memset(&c, 0, sizeof(c));
+    c.n_levels = m->n_levels;
+    c.table_dtype = m->table_dtype;
+    c.phi = m->phi;
+    c.table = m->table;
+    c.weights = m->weights;
+    c.nodes = reinterpret_cast<const BvhNode*>(m->bvh_nodes);
+    c.tris = reinterpret_cast<const BvhTri*>(m->bvh_tris);
+    c.n_tris = m->n_tris;
+    if (need_table) require(m->phi && m->table, "phi and table must be set");
+    if (need_bvh) {
+        require(m->n_tris >= 0, "n_tris must be >= 0");
+        require(m->n_tris == 0 || (m->bvh_nodes && m->bvh_tris), "bvh images must be set");
+    }
+    for (int l = 0; l < m->n_levels; ++l) {
+        const inrf_level_desc& d = m->levels[l];
+        require(d.res >= 1 && d.res <= 4096, "level resolution must be in [1, 4096]");
+        require(d.mbar >= 1 && d.mbar <= 1024, "mbar must be in [1, 1024]");
+        require(d.rbar >= 1 && d.rbar <= 4096, "rbar must be in [1, 4096]");
+        require(int64_t(d.rbar) * d.rbar * d.rbar < (int64_t(1) << 31), "rbar^3 must fit 31 bits");
+        require(d.phi_offset >= 0 && d.slot_offset >= 0, "negative level offsets");
+        LevelC& L = c.lv[l];
+        L.res = d.res;
+        L.mbar = d.mbar;
+        L.rbar = d.rbar;
+        L.inv_mbar = 1.f / float(d.mbar);
+        L.inv_rbar = 1.f / float(d.rbar);
+        L.phi_off = d.phi_offset;
+        L.slot_off = d.slot_offset;
+    }
+    return c;
+}
+
+void launch_check(const char* what) { check_hip(hipGetLastError(), what); }
+
+int shade_grid() { return num_cus() * 2; }
+
+// Kernels whose dynamic LDS may exceed the default 64 KB window.
+template <class K>
+void allow_lds(K kernel, size_t bytes) {
+    if (bytes > 65536)
+        check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)),
+                  "hipFuncSetAttribute");
+}
+
+size_t shade_lds(int32_t precision, int d_in) {
+    if (precision == INRF_PREC_FP32) return size_t(f32_lds_floats(d_in)) * 4;
+    const int C = lp_chunks(d_in);
+    return size_t(lp_lds_vecs(d_in)) * 16 + size_t(4 * 64 * (32 * C + 8)) * 2;
+}
+
+template <class TableT>
+void launch_shade(const ModelC& c, int32_t precision, const HitRec* recs, const int32_t* counter, float* rgba,
+                  hipStream_t s) {
+    const int d_in = 2 * c.n_levels + INRF_SH_DIM;
+    const size_t lds = shade_lds(precision, d_in);
+    const int C = lp_chunks(d_in);
+    const dim3 grid(shade_grid()), block(kThreads);
+    if (precision == INRF_PREC_FP32) {
+        hipLaunchKernelGGL(k_shade_f32<TableT>, grid, block, lds, s, c, recs, counter, rgba);
+        return;
+    }
+#define INRF_LP_CASE(TT, CC)                                                                     \
+    case CC:                                                                                     \
+        allow_lds(k_shade_lp<TableT, TT, CC>, lds);                                              \
+        hipLaunchKernelGGL((k_shade_lp<TableT, TT, CC>), grid, block, lds, s, c, recs, counter, rgba); \
+        break;
+    if (precision == INRF_PREC_FP16) {
+        switch (C) {
+            INRF_LP_CASE(_Float16, 1)
+            INRF_LP_CASE(_Float16, 2)
+            INRF_LP_CASE(_Float16, 3)
+            default: fail(INRF_E_UNSUPPORTED, "input width");
+        }
+    } else {
+        switch (C) {
+            INRF_LP_CASE(__bf16, 1)
+            INRF_LP_CASE(__bf16, 2)
+            INRF_LP_CASE(__bf16, 3)
+            default: fail(INRF_E_UNSUPPORTED, "input width");
+        }
+    }
+#undef INRF_LP_CASE
+}
+
+void check_precision(int32_t p) {
+    require(p == INRF_PREC_FP32 || p == INRF_PREC_FP16 || p == INRF_PREC_BF16, "unknown precision");
+}
+
+void run_path(const inrf_model* m, int32_t precision, const CamC* cam, const float* ray_o, const float* ray_d,
+              int64_t n, float* rgba, float* depth, int32_t* tri, void* ws, int64_t ws_bytes, void* stream) {
+    check_precision(precision);
+    const ModelC c = make_model(m, true, true);
+    require(m->weights != nullptr, "weights must be set");
+    require(rgba != nullptr, "rgba is NULL");
+    require(ws != nullptr, "workspace is NULL");
+    require((reinterpret_cast<uintptr_t>(ws) & 15) == 0 && (reinterpret_cast<uintptr_t>(rgba) & 15) == 0,
+            "rgba and workspace must be 16-byte aligned");
+    if (ws_bytes < inrf_workspace_size(n))
+        fail(INRF_E_SIZE, "workspace of " + std::to_string(ws_bytes) + " bytes < " +
+                              std::to_string(inrf_workspace_size(n)) + " needed");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (n == 0) return;
+    int32_t* counter = reinterpret_cast<int32_t*>(ws);
+    HitRec* recs = reinterpret_cast<HitRec*>(reinterpret_cast<char*>(ws) + kWsHeader);
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, counter);
+    launch_check("k_reset");
+    TraceArgs a{ray_o, ray_d, n, rgba, depth, tri, recs, counter};
+    if (cam) {
+        const int tiles = cam->tiles_x * ((cam->H + kTile - 1) / kTile);
+        hipLaunchKernelGGL(k_trace<true>, dim3(tiles), dim3(kThreads), 0, s, c, *cam, a);
+    } else {
+        CamC none;
+        std::memset(&none, 0, sizeof(none));
+        hipLaunchKernelGGL(k_trace<false>, dim3(unsigned((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, c,
+                           none, a);
+    }
+    launch_check("k_trace");
+    if (c.table_dtype == INRF_F32) launch_shade<float>(c, precision, recs, counter, rgba, s);
+    else launch_shade<__half>(c, precision, recs, counter, rgba, s);
+    launch_check("k_shade");
+}
+
+}  // namespace
+}  // namespace inrf
+
+using namespace inrf;
+
+extern "C" {
+
+int64_t inrf_workspace_size(int64_t n_rays) {
+    if (n_rays < 0) return -1;
+    return kWsHeader + n_rays * int64_t(sizeof(dev::HitRec));
+}
+
+inrf_status inrf_render(const inrf_model* m, int32_t precision, const inrf_camera* cam, float* rgba, float* depth,
+                        int32_t* tri, void* ws, int64_t ws_bytes, void* stream) {
+    return guarded("inrf_render", [&] {
+        require(cam != nullptr, "camera is NULL");
+        require(cam->width >= 1 && cam->height >= 1, "image size must be positive");
+        require(int64_t(cam->width) * cam->height <= (int64_t(1) << 31) - 1, "image too large");
+        dev::CamC c;
+        for (int k = 0; k < 3; ++k) {
+            c.o[k] = cam->origin[k];
+            c.r[k] = cam->right[k];
+            c.u[k] = cam->up[k];
+            c.f[k] = cam->forward[k];
+        }
+        require(std::isfinite(cam->tan_half_fov_y) && cam->tan_half_fov_y > 0.f, "tan_half_fov_y must be > 0");
+        c.tan_y = cam->tan_half_fov_y;
+        c.tan_x = cam->tan_half_fov_y * float(cam->width) / float(cam->height);
+        c.W = cam->width;
+        c.H = cam->height;
+        c.tiles_x = (cam->width + dev::kTile - 1) / dev::kTile;
+        run_path(m, precision, &c, nullptr, nullptr, int64_t(cam->width) * cam->height, rgba, depth, tri, ws,
+                 ws_bytes, stream);
+    });
+}
+
+inrf_status inrf_forward(const inrf_model* m, int32_t precision, const float* ray_o, const float* ray_d, int64_t n,
+                         float* rgba, float* depth, int32_t* tri, void* ws, int64_t ws_bytes, void* stream) {
+    return guarded("inrf_forward", [&] {
+        require(n >= 0 && n <= (int64_t(1) << 31) - 1, "n must be in [0, 2^31)");
+        require(n == 0 || (ray_o && ray_d), "ray buffers are NULL");
+        run_path(m, precision, nullptr, ray_o, ray_d, n, rgba, depth, tri, ws, ws_bytes, stream);
+    });
+}
+
+inrf_status inrf_trace(const inrf_model* m, const float* ray_o, const float* ray_d, int64_t n, int32_t* tri,
+                       float* t, void* stream) {
+    return guarded("inrf_trace", [&] {
+        const dev::ModelC c = make_model(m, false, true);
+        require(n >= 0 && n <= (int64_t(1) << 31) - 1, "n must be in [0, 2^31)");
+        require(n == 0 || (ray_o && ray_d && tri && t), "NULL buffer");
+        if (n == 0) return;
+        dev::TraceArgs a{ray_o, ray_d, n, nullptr, t, tri, nullptr, nullptr};
+        dev::CamC none;
+        std::memset(&none, 0, sizeof(none));
+        hipLaunchKernelGGL(dev::k_trace<false>, dim3(unsigned((n + dev::kThreads - 1) / dev::kThreads)),
+                           dim3(dev::kThreads), 0, reinterpret_cast<hipStream_t>(stream), c, none, a);
+        launch_check("k_trace");
+    });
+}
+
+inrf_status inrf_encode(const inrf_model* m, const float* x, int64_t n, float* enc, int32_t* slots, void* stream) {
+    return guarded("inrf_encode", [&] {
+        const dev::ModelC c = make_model(m, true, false);
+        require(n >= 0 && n <= (int64_t(1) << 31) - 1, "n must be in [0, 2^31)");
+        require(n == 0 || (x && enc), "NULL buffer");
+        if (n == 0) return;
+        const dim3 grid(unsigned((n + dev::kThreads - 1) / dev::kThreads)), block(dev::kThreads);
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        if (c.table_dtype == INRF_F32) hipLaunchKernelGGL(dev::k_encode<float>, grid, block, 0, s, c, x, n, enc, slots);
+        else hipLaunchKernelGGL(dev::k_encode<__half>, grid, block, 0, s, c, x, n, enc, slots);
+        launch_check("k_encode");
+    });
+}
+
+inrf_status inrf_mlp(const inrf_model* m, int32_t precision, const float* in, int64_t n, float* rgba, void* stream) {
+    return guarded("inrf_mlp", [&] {
+        check_precision(precision);
+        require(m != nullptr && m->weights != nullptr, "model weights must be set");
+        require(m->n_levels >= 1 && m->n_levels <= INRF_MAX_LEVELS, "n_levels must be in [1, 32]");
+        require(n >= 0 && n <= (int64_t(1) << 31) - 1, "n must be in [0, 2^31)");
+        require(n == 0 || (in && rgba), "NULL buffer");
+        require((reinterpret_cast<uintptr_t>(rgba) & 15) == 0, "rgba must be 16-byte aligned");
+        if (n == 0) return;
+        dev::ModelC c;
+        std::memset(&c, 0, sizeof(c));
+        c.n_levels = m->n_levels;
+        c.weights = m->weights;
+        const int d_in = 2 * c.n_levels + INRF_SH_DIM;
+        const size_t lds = shade_lds(precision, d_in);
+        const int64_t waves = (n + 63) / 64;
+        const unsigned grid = unsigned(std::min<int64_t>((waves + 3) / 4, int64_t(num_cus()) * 4));
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        const int C = dev::lp_chunks(d_in);
+        if (precision == INRF_PREC_FP32) {
+            hipLaunchKernelGGL(dev::k_mlp_f32, dim3(grid), dim3(dev::kThreads), lds, s, c, in, n, rgba);
+        } else if (precision == INRF_PREC_FP16) {
+            allow_lds(dev::k_mlp_lp<_Float16, 3>, lds);
+            if (C == 1) hipLaunchKernelGGL((dev::k_mlp_lp<_Float16, 1>), dim3(grid), dim3(dev::kThreads), lds, s, c, in, n, rgba);
+            else if (C == 2) hipLaunchKernelGGL((dev::k_mlp_lp<_Float16, 2>), dim3(grid), dim3(dev::kThreads), lds, s, c, in, n, rgba);
+            else hipLaunchKernelGGL((dev::k_mlp_lp<_Float16, 3>), dim3(grid), dim3(dev::kThreads), lds, s, c, in, n, rgba);
+        } else {
+            allow_lds(dev::k_mlp_lp<__bf16, 3>, lds);
+            if (C == 1) hipLaunchKernelGGL((dev::k_mlp_lp<__bf16, 1>), dim3(grid), dim3(dev::kThreads), lds, s, c, in, n, rgba);
+            else if (C == 2) hipLaunchKernelGGL((dev::k_mlp_lp<__bf16, 2>), dim3(grid), dim3(dev::kThreads), lds, s, c, in, n, rgba);
+            else hipLaunchKernelGGL((dev::k_mlp_lp<__bf16, 3>), dim3(grid), dim3(dev::kThreads), lds, s, c, in, n, rgba);
+        }
+        launch_check("k_mlp");
+    });
+}
+
+}  // extern "C"

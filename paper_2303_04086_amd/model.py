@@ -1,0 +1,259 @@
+"""Python binding of libinrf: host builders, a device-resident model, and the
+render / forward / trace / encode / mlp calls.
+
+PyTorch provides device memory and the stream; every step of the path runs in
+the library's kernels.  There is no fallback: a missing library or a missing
+GPU raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Callable, Optional, Sequence
+
+import numpy as np
+
+from . import _lib as L
+
+
+@dataclass
+class PshLevel:
+    res: int
+    mbar: int
+    rbar: int
+    restarts: int
+    keys: np.ndarray   # int64 [n] linear keys (z*(N+1)+y)*(N+1)+x, ascending
+    phi: np.ndarray    # uint32 [rbar^3] packed offsets
+    slots: np.ndarray  # int32 [n] slot of each key
+
+    def vertices(self) -> np.ndarray:
+        M = self.res + 1
+        k = self.keys
+        return np.stack([k % M, (k // M) % M, k // (M * M)], axis=1)
+
+
+def psh_params(**kw) -> L.PshParams:
+    p = L.PshParams()
+    L.lib().inrf_psh_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _levels_out(h) -> list:
+    lib = L.lib()
+    out = []
+    try:
+        for l in range(lib.inrf_psh_levels(h)):
+            info = L.PshLevelInfo()
+            L.check(lib.inrf_psh_level(h, l, ctypes.byref(info), None, None, None))
+            keys = np.empty(info.n_keys, np.int64)
+            phi = np.empty(info.n_phi, np.uint32)
+            slots = np.empty(info.n_keys, np.int32)
+            L.check(lib.inrf_psh_level(h, l, ctypes.byref(info), L.ptr(keys), L.ptr(phi), L.ptr(slots)))
+            out.append(PshLevel(info.res, info.mbar, info.rbar, info.restarts, keys, phi, slots))
+    finally:
+        lib.inrf_psh_free(h)
+    return out
+
+
+def _mesh_args(verts, tris):
+    v = np.ascontiguousarray(verts, np.float32).reshape(-1, 3)
+    t = np.ascontiguousarray(tris, np.int32).reshape(-1, 3)
+    return v, t
+
+
+def build_psh(verts, tris, res: Sequence[int], **params) -> list:
+    """Voxelise the proxy at each resolution and build each level's PSH."""
+    v, t = _mesh_args(verts, tris)
+    r = np.ascontiguousarray(res, np.int32)
+    p = psh_params(**params)
+    h = ctypes.c_void_p()
+    L.check(L.lib().inrf_build_psh(L.ptr(v), len(v), L.ptr(t), len(t), len(r), L.ptr(r), ctypes.byref(p),
+                                   ctypes.byref(h)))
+    return _levels_out(h)
+
+
+def build_psh_keys(res: int, keys, **params) -> PshLevel:
+    """Build one level's PSH from a caller-supplied ascending key list."""
+    k = np.ascontiguousarray(keys, np.int64)
+    p = psh_params(**params)
+    h = ctypes.c_void_p()
+    L.check(L.lib().inrf_build_psh_keys(int(res), L.ptr(k), len(k), ctypes.byref(p), ctypes.byref(h)))
+    return _levels_out(h)[0]
+
+
+@dataclass
+class BvhImage:
+    nodes: np.ndarray  # uint8
+    tris: np.ndarray   # uint8
+    n_nodes: int
+    depth: int
+
+
+def build_bvh(verts, tris) -> BvhImage:
+    v, t = _mesh_args(verts, tris)
+    lib = L.lib()
+    h = ctypes.c_void_p()
+    L.check(lib.inrf_build_bvh(L.ptr(v), len(v), L.ptr(t), len(t), ctypes.byref(h)))
+    try:
+        info = L.BvhInfo()
+        L.check(lib.inrf_bvh_get_info(h, ctypes.byref(info)))
+        nodes = np.zeros(max(info.node_bytes, 64), np.uint8)
+        tri = np.zeros(max(info.tri_bytes, 48), np.uint8)
+        L.check(lib.inrf_bvh_copy(h, L.ptr(nodes), L.ptr(tri)))
+        return BvhImage(nodes, tri, info.n_nodes, info.depth)
+    finally:
+        lib.inrf_bvh_free(h)
+
+
+PRECISIONS = {"fp32": L.PREC_FP32, "fp16": L.PREC_FP16, "bf16": L.PREC_BF16}
+TABLES = {"f32": L.INRF_F32, "f16": L.INRF_F16}
+
+
+def _camera_desc(cam) -> L.CameraDesc:
+    c = L.CameraDesc()
+    for name in ("origin", "right", "up", "forward"):
+        getattr(c, name)[:] = [float(x) for x in np.asarray(getattr(cam, name), np.float32)]
+    c.tan_half_fov_y = float(np.float32(cam.tan_half_fov_y))
+    c.width, c.height = int(cam.width), int(cam.height)
+    return c
+
+
+class Renderer:
+    """A device-resident i-NOLF object: PSH offset tables and feature tables
+    (FP32 and/or FP16), FP32 network weights, and the proxy BVH."""
+
+    def __init__(self, verts, tris, res: Sequence[int], weights: Sequence[np.ndarray],
+                 features: Callable[[int, PshLevel], np.ndarray], tables=("f32",), device="cuda",
+                 psh_levels: Optional[list] = None, **psh_kw):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the render path runs only on the device")
+        self.torch = torch
+        self.device = torch.device(device)
+        self.res = [int(r) for r in res]
+        self.n_levels = len(self.res)
+        self.levels = psh_levels if psh_levels is not None else build_psh(verts, tris, self.res, **psh_kw)
+        d_in = 2 * self.n_levels + L.SH_DIM
+        w = [np.asarray(x, np.float32) for x in weights]
+        if [x.shape for x in w] != [(L.HIDDEN, d_in), (L.HIDDEN, L.HIDDEN), (L.OUT, L.HIDDEN)]:
+            raise ValueError(f"weights must be shaped [64,{d_in}], [64,64], [4,64]")
+        self.weights = torch.from_numpy(np.concatenate([x.reshape(-1) for x in w])).to(self.device)
+        phi_off, slot_off = 0, 0
+        self.level_desc = []
+        for lv in self.levels:
+            self.level_desc.append((lv.res, lv.mbar, lv.rbar, phi_off, slot_off))
+            phi_off += len(lv.phi)
+            slot_off += lv.mbar ** 3
+        self.n_slots = slot_off
+        self.phi = torch.from_numpy(np.concatenate([lv.phi for lv in self.levels]).view(np.int32)).to(self.device)
+        host = np.zeros((slot_off, L.FEATURES), np.float32)
+        for l, lv in enumerate(self.levels):
+            f = np.asarray(features(l, lv), np.float32)
+            host[self.level_desc[l][4] + lv.slots.astype(np.int64)] = f
+        self.tables = {}
+        t32 = torch.from_numpy(host)
+        for name in tables:
+            if name == "f32":
+                self.tables[name] = t32.to(self.device)
+            elif name == "f16":
+                self.tables[name] = t32.to(torch.float16).to(self.device)
+            else:
+                raise ValueError(name)
+        del host, t32
+        self.bvh = build_bvh(verts, tris)
+        self.n_tris = int(np.asarray(tris).reshape(-1, 3).shape[0])
+        self.bvh_nodes = torch.from_numpy(self.bvh.nodes).to(self.device)
+        self.bvh_tris = torch.from_numpy(self.bvh.tris).to(self.device)
+        self._ws = None
+        self._descs = {}
+
+    # -- descriptors -------------------------------------------------------
+    def desc(self, table: str = "f32") -> L.ModelDesc:
+        if table not in self._descs:
+            if table not in self.tables:
+                raise KeyError(f"table {table!r} not resident (have {list(self.tables)})")
+            m = L.ModelDesc()
+            m.n_levels = self.n_levels
+            m.table_dtype = TABLES[table]
+            for l, (res, mbar, rbar, po, so) in enumerate(self.level_desc):
+                m.levels[l].res, m.levels[l].mbar, m.levels[l].rbar = res, mbar, rbar
+                m.levels[l].phi_offset, m.levels[l].slot_offset = po, so
+            m.phi = self.phi.data_ptr()
+            m.table = self.tables[table].data_ptr()
+            m.weights = self.weights.data_ptr()
+            m.bvh_nodes = self.bvh_nodes.data_ptr()
+            m.bvh_tris = self.bvh_tris.data_ptr()
+            m.n_tris = self.n_tris
+            self._descs[table] = m
+        return self._descs[table]
+
+    def workspace(self, n_rays: int):
+        need = int(L.lib().inrf_workspace_size(n_rays))
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = self.torch.empty(need, dtype=self.torch.uint8, device=self.device)
+        return self._ws
+
+    def _stream(self, stream):
+        s = stream if stream is not None else self.torch.cuda.current_stream(self.device)
+        return ctypes.c_void_p(s.cuda_stream)
+
+    # -- calls -------------------------------------------------------------
+    def render(self, cam, precision="fp32", table="f32", rgba=None, depth=None, tri=None, stream=None):
+        torch = self.torch
+        n = int(cam.width) * int(cam.height)
+        if rgba is None:
+            rgba = torch.empty((int(cam.height), int(cam.width), 4), dtype=torch.float32, device=self.device)
+        ws = self.workspace(n)
+        c = _camera_desc(cam)
+        L.check(L.lib().inrf_render(ctypes.byref(self.desc(table)), PRECISIONS[precision], ctypes.byref(c),
+                                    L.ptr(rgba), L.ptr(depth), L.ptr(tri), L.ptr(ws), ws.numel(),
+                                    self._stream(stream)))
+        return rgba
+
+    def forward(self, o, d, precision="fp32", table="f32", depth=None, tri=None, rgba=None, stream=None):
+        torch = self.torch
+        o = o.contiguous()
+        d = d.contiguous()
+        n = o.shape[0]
+        if rgba is None:
+            rgba = torch.empty((n, 4), dtype=torch.float32, device=self.device)
+        ws = self.workspace(n)
+        L.check(L.lib().inrf_forward(ctypes.byref(self.desc(table)), PRECISIONS[precision], L.ptr(o), L.ptr(d), n,
+                                     L.ptr(rgba), L.ptr(depth), L.ptr(tri), L.ptr(ws), ws.numel(),
+                                     self._stream(stream)))
+        return rgba
+
+    def trace(self, o, d, stream=None):
+        torch = self.torch
+        o = o.contiguous()
+        d = d.contiguous()
+        n = o.shape[0]
+        tri = torch.empty(n, dtype=torch.int32, device=self.device)
+        t = torch.empty(n, dtype=torch.float32, device=self.device)
+        L.check(L.lib().inrf_trace(ctypes.byref(self.desc(next(iter(self.tables)))), L.ptr(o), L.ptr(d), n,
+                                   L.ptr(tri), L.ptr(t), self._stream(stream)))
+        return tri, t
+
+    def encode(self, x, table="f32", slots=False, stream=None):
+        torch = self.torch
+        x = x.contiguous()
+        n = x.shape[0]
+        enc = torch.empty((n, 2 * self.n_levels), dtype=torch.float32, device=self.device)
+        sl = torch.empty((n, self.n_levels, 8), dtype=torch.int32, device=self.device) if slots else None
+        L.check(L.lib().inrf_encode(ctypes.byref(self.desc(table)), L.ptr(x), n, L.ptr(enc), L.ptr(sl),
+                                    self._stream(stream)))
+        return (enc, sl) if slots else enc
+
+    def mlp(self, inputs, precision="fp32", out=None, stream=None):
+        torch = self.torch
+        inputs = inputs.contiguous()
+        n = inputs.shape[0]
+        if out is None:
+            out = torch.empty((n, 4), dtype=torch.float32, device=self.device)
+        L.check(L.lib().inrf_mlp(ctypes.byref(self.desc(next(iter(self.tables)))), PRECISIONS[precision],
+                                 L.ptr(inputs), n, L.ptr(out), self._stream(stream)))
+        return out

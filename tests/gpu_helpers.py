@@ -1,0 +1,32 @@
+"""Shared set-up of the GPU tests: a device model of a synthetic workload and
+comparison helpers.  Inputs come from `synth`; expected values from `oracle`."""
+import numpy as np
+
+import synth
+
+
+def feature_fn(w, kind="normal", sigma=1e-2):
+    return lambda l, lv: synth.feature_values(w.feature_seed, l, lv.keys, F=w.F, kind=kind, sigma=sigma)
+
+
+def make_renderer(w, tables=("f32", "f16"), kind="normal", sigma=1e-2):
+    import paper_2303_04086_amd as P
+    return P.Renderer(w.verts, w.tris, w.res, w.weights, feature_fn(w, kind, sigma), tables=tables,
+                      dilate=w.dilate, seed=w.psh_seed)
+
+
+def psnr(a, b):
+    mse = float(np.mean((np.asarray(a, np.float64) - np.asarray(b, np.float64)) ** 2))
+    return float("inf") if mse == 0 else 10.0 * np.log10(1.0 / mse)
+
+
+def compare_hits(gpu_tri, ora, max_amb_frac=2e-3):
+    """Triangle ids bit-exact on rays the oracle calls unambiguous; returns
+    the mask of rays whose hit/miss agrees."""
+    gpu_tri = np.asarray(gpu_tri).reshape(-1)
+    amb = ora["ambiguous"]
+    clear = ~amb
+    bad = np.nonzero(clear & (gpu_tri != ora["tri"]))[0]
+    assert len(bad) == 0, f"{len(bad)} unambiguous rays differ, e.g. {bad[:5]} gpu={gpu_tri[bad[:5]]} oracle={ora['tri'][bad[:5]]}"
+    assert amb.mean() <= max_amb_frac, amb.mean()
+    return (gpu_tri >= 0) == (ora["tri"] >= 0)

@@ -1,0 +1,134 @@
+"""Host side of libinrf (no GPU): exports, PSH / occupancy bit-identity with
+the oracle, BVH invariants, argument errors."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+P = pytest.importorskip("paper_2303_04086_amd")
+from paper_2303_04086_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "inrf.h")).read()
+    declared = set(re.findall(r"\b(inrf_[a-z_]+)\s*\(", hdr))
+    lib = L.lib()
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(L.EXPORTED)
+    assert lib.inrf_version() >= 100
+
+
+def test_psh_identical_to_oracle_on_tiny_workload(tiny, tiny_keys):
+    levels = P.build_psh(tiny.verts, tiny.tris, tiny.res)
+    for N, k, lv in zip(tiny.res, tiny_keys, levels):
+        M = N + 1
+        assert np.array_equal((k[:, 2] * M + k[:, 1]) * M + k[:, 0], lv.keys)
+        O = oracle.build_psh_level(k, N, seed=1)
+        assert (lv.mbar, lv.rbar) == (O.mbar, O.rbar)
+        assert np.array_equal(lv.phi, O.phi)
+        assert np.array_equal(lv.slots.astype(np.int64), O.slots)
+
+
+def test_psh_identical_to_oracle_other_parameters(tiny_keys, tiny):
+    k = tiny_keys[1]
+    N = tiny.res[1]
+    M = N + 1
+    lin = (k[:, 2] * M + k[:, 1]) * M + k[:, 0]
+    for kw in ({"seed": 7, "load_pct": 95, "bucket_keys": 6}, {"seed": 3, "load_pct": 60, "bucket_keys": 1},
+               {"seed": 1, "load_pct": 100, "bucket_keys": 6, "n_random": 0}):
+        lv = P.build_psh_keys(N, lin, **kw)
+        O = oracle.build_psh_level(k, N, **kw)
+        assert (lv.mbar, lv.rbar, lv.restarts >= 0) == (O.mbar, O.rbar, True)
+        assert np.array_equal(lv.phi, O.phi), kw
+        assert np.array_equal(lv.slots.astype(np.int64), O.slots), kw
+
+
+def test_occupancy_identical_to_oracle_on_random_soup():
+    rng = np.random.default_rng(5)
+    v = synth.quantize_vertices(rng.uniform(0.05, 0.95, (60, 3)))
+    t = rng.integers(0, 60, (20, 3)).astype(np.int32)
+    for N, dil in ((7, 0), (13, 1), (20, 2)):
+        lv = P.build_psh(v, t, [N], dilate=dil)[0]
+        k = oracle.shell_keys(v, t, N, dil)
+        M = N + 1
+        assert np.array_equal((k[:, 2] * M + k[:, 1]) * M + k[:, 0], lv.keys), (N, dil)
+
+
+def test_bvh_invariants(tiny):
+    v, t = synth.displaced_sphere(12)
+    b = P.build_bvh(v, t)
+    nodes = b.nodes.view(np.float32).reshape(-1, 16)
+    refs = b.nodes.view(np.int32).reshape(-1, 16)[:, 12:14]
+    tri_img = b.tris.view(np.float32).reshape(-1, 12)
+    idx = b.tris.view(np.int32).reshape(-1, 12)[:, 3]
+    assert sorted(idx.tolist()) == list(range(len(t)))          # every triangle exactly once
+    V = v.astype(np.float32)
+    assert np.array_equal(tri_img[:, 0:3], V[t[idx, 0]]) and np.array_equal(tri_img[:, 8:11], V[t[idx, 2]])
+    seen = []
+
+    def walk(ref, lo, hi, depth):
+        if ref < 0:
+            code = ~ref
+            first, count = code >> 3, code & 7
+            assert count <= 4
+            for i in range(first, first + count):
+                p = tri_img[i].reshape(3, 4)[:, :3]
+                assert np.all(p >= lo) and np.all(p <= hi)
+                seen.append(i)
+            return depth
+        n = nodes[ref]
+        d = 0
+        for side, (a, z) in enumerate(((n[0:3], n[3:6]), (n[6:9], n[9:12]))):
+            if lo is not None:
+                assert np.all(a >= lo) and np.all(z <= hi)          # children inside the parent
+            d = max(d, walk(refs[ref][side], a, z, depth + 1))
+        return d
+
+    depth = walk(0, None, None, 1)
+    assert sorted(seen) == list(range(len(t))) and depth <= 32 and depth == b.depth
+
+
+def test_argument_errors():
+    lib = L.lib()
+    h = ctypes.c_void_p()
+    p = P.psh_params()
+    bad_v = np.array([[0.1, 0.2, 0.3]], np.float32)          # 0.1 is off the 2^-16 lattice
+    t = np.array([[0, 0, 0]], np.int32)
+    r = np.array([8], np.int32)
+    assert lib.inrf_build_psh(L.ptr(bad_v), 1, L.ptr(t), 1, 1, L.ptr(r), ctypes.byref(p), ctypes.byref(h)) == L.INRF_E_INVALID
+    assert b"2^-16" in lib.inrf_last_error()
+    good_v = synth.quantize_vertices(bad_v)
+    t_bad = np.array([[0, 0, 5]], np.int32)
+    assert lib.inrf_build_psh(L.ptr(good_v), 1, L.ptr(t_bad), 1, 1, L.ptr(r), ctypes.byref(p), ctypes.byref(h)) == L.INRF_E_INVALID
+    r0 = np.array([0], np.int32)
+    assert lib.inrf_build_psh(L.ptr(good_v), 1, L.ptr(t), 1, 1, L.ptr(r0), ctypes.byref(p), ctypes.byref(h)) == L.INRF_E_INVALID
+    p.load_pct = 0
+    assert lib.inrf_build_psh(L.ptr(good_v), 1, L.ptr(t), 1, 1, L.ptr(r), ctypes.byref(p), ctypes.byref(h)) == L.INRF_E_INVALID
+    keys = np.array([5, 3], np.int64)
+    assert lib.inrf_build_psh_keys(4, L.ptr(keys), 2, ctypes.byref(P.psh_params()), ctypes.byref(h)) == L.INRF_E_INVALID
+    # device calls validate before touching the device
+    m = L.ModelDesc()
+    m.n_levels = 0
+    assert lib.inrf_encode(ctypes.byref(m), None, 0, None, None, None) == L.INRF_E_INVALID
+    m.n_levels = 1
+    m.table_dtype = 7
+    assert lib.inrf_encode(ctypes.byref(m), None, 0, None, None, None) == L.INRF_E_INVALID
+    assert lib.inrf_workspace_size(-1) == -1
+    assert lib.inrf_workspace_size(1000) > 1000 * 16
+
+
+def test_empty_mesh_builds():
+    v = np.zeros((0, 3), np.float32)
+    t = np.zeros((0, 3), np.int32)
+    lv = P.build_psh(v, t, [4])[0]
+    assert len(lv.keys) == 0 and lv.mbar == 2  # smallest with 80*m^3 >= 100*max(n, 1)
+    b = P.build_bvh(v, t)
+    assert b.n_nodes == 1
