@@ -1,0 +1,257 @@
+#!/usr/bin/env python
+"""Benchmark of the i-NOLF one-query-per-ray render path on one MI355X.
+
+Workload: one displaced-sphere object (100,820-triangle proxy, 16 PSH levels
+16..2048, F=2, MLP 48-64-64-4) rendered at 3840x2160 from 8 cameras on a
+sphere of radius 2 (synthetic stand-in for one trained object; see the design
+notes).  A step is one full frame through the whole path: ray generation,
+BVH closest hit, hit compaction, PSH gather + trilinear + SH16 + MLP, RGBA
+output.  `value` is Mrays/s (all primary rays, hits and misses) of the
+FP16-table / FP16-MFMA path over the timed region; the FP32 path is measured
+the same way and reported beside it.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mrays/s at 3840x2160 one-object render (FP32 vs FP16-MFMA); p99 frame latency"
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"fp16": 2500.0, "bf16": 2500.0, "fp32": 157.3}
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def requested_bytes_per_hit(n_levels: int, table: str) -> int:
+    """Gather bytes one hit ray asks for: per level 8 corners x (F features
+    of the table type + one 4-byte offset entry)."""
+    return 8 * n_levels * (2 * (4 if table == "f32" else 2) + 4)
+
+
+def mlp_flops(d_in: int) -> int:
+    return 2 * (d_in * 64 + 64 * 64 + 64 * 4)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2303_04086_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def run_frames(torch, R, cams, prec, table, steps, warmup):
+    rgba = torch.empty((cams[0].height, cams[0].width, 4), dtype=torch.float32, device="cuda")
+    for i in range(warmup):
+        R.render(cams[i % len(cams)], prec, table, rgba=rgba)
+    torch.cuda.synchronize()
+    hits = []
+    for c in cams:
+        R.render(c, prec, table, rgba=rgba)
+        torch.cuda.synchronize()
+        hits.append(R.hit_count())
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    for trip in ev:                      # create the underlying events before use
+        for e in trip:
+            e.record()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        R.render(cams[i % len(cams)], prec, table, rgba=rgba, events=ev[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    frame = [ev[i][0].elapsed_time(ev[i][2]) for i in range(steps)]
+    trace = [ev[i][0].elapsed_time(ev[i][1]) for i in range(steps)]
+    shade = [ev[i][1].elapsed_time(ev[i][2]) for i in range(steps)]
+    shade_hits = [hits[i % len(cams)] for i in range(steps)]
+    return {"wall_s": wall, "frame_ms": frame, "trace_ms": trace, "shade_ms": shade, "hits": shade_hits,
+            "hits_per_camera": hits}
+
+
+def pct(v, q):
+    s = sorted(v)
+    return s[min(len(s) - 1, int(round(q / 100.0 * (len(s) - 1))))]
+
+
+def summarize(r, W, H, steps, n_levels, table):
+    rays = W * H * steps
+    shade_s = sum(r["shade_ms"]) / 1e3
+    bytes_req = sum(r["hits"]) * requested_bytes_per_hit(n_levels, table)
+    achieved = bytes_req / shade_s / 1e9
+    return {
+        "value": round(rays / r["wall_s"] / 1e6, 2),
+        "ms_per_step": round(r["wall_s"] / steps * 1e3, 4),
+        "p50_ms": round(pct(r["frame_ms"], 50), 4),
+        "p99_ms": round(pct(r["frame_ms"], 99), 4),
+        "trace_ms_avg": round(sum(r["trace_ms"]) / steps, 4),
+        "shade_ms_avg": round(sum(r["shade_ms"]) / steps, 4),
+        "hit_rays_per_frame_avg": round(sum(r["hits"]) / steps, 1),
+        "hit_Mrays_per_s": round(sum(r["hits"]) / r["wall_s"] / 1e6, 2),
+        "shade_requested_GBps": round(achieved, 1),
+    }
+
+
+def mlp_bench(torch, R, prec, n, reps=5):
+    d_in = 2 * R.n_levels + 16
+    x = torch.randn((n, d_in), device="cuda") * 0.1
+    out = torch.empty((n, 4), device="cuda")
+    R.mlp(x, prec, out=out)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        R.mlp(x, prec, out=out)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    tf = n * mlp_flops(d_in) / (ms / 1e3) / 1e12
+    del x, out
+    return {"rays": n, "ms": round(ms, 4), "TFLOPs": round(tf, 2), "peak": MFMA_PEAK_TFLOPS[prec],
+            "utilisation": round(tf / MFMA_PEAK_TFLOPS[prec], 4)}
+
+
+def cpu_baseline(w, n_sample, seed=11):
+    """The FP64 oracle, as it stands, on a seeded sample of pixels of camera 0."""
+    import numpy as np
+    import oracle
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        limiter = None
+    cam = w.cameras[0]
+    rng = np.random.default_rng(seed)
+    rows = rng.integers(0, cam.height, n_sample)
+    cols = rng.integers(0, cam.width, n_sample)
+    m = oracle.Model.from_workload(w, materialize=False, check_keys=False)
+    t0 = time.perf_counter()
+    oracle.render_camera(m, cam, rows, cols)
+    dt = time.perf_counter() - t0
+    if limiter is not None:
+        limiter.unregister() if hasattr(limiter, "unregister") else None
+    return {"value": round(n_sample / dt / 1e6, 6), "unit": "Mrays/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_sample} seeded random pixels of camera 0 at {cam.width}x{cam.height}, "
+                      f"full path in FP64 ({dt:.1f} s)"}
+
+
+def load_traffic(kernel: str):
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    e = t.get(kernel)
+    if not e or e.get("source_hash") != source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--width", type=int, default=3840)
+    ap.add_argument("--height", type=int, default=2160)
+    ap.add_argument("--cpu-sample", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mlp", action="store_true")
+    ap.add_argument("--mlp-rays", type=int, default=1 << 24)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this path has no multi-GPU mode (rays are independent, "
+              "so a frame would shard by tiles with no exchange); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import synth
+    import paper_2303_04086_amd as P
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+
+    W, H = args.width, args.height
+    w = synth.workload_object(W, H)
+    log(f"workload {w.name}: {len(w.tris)} triangles, levels {w.res}")
+    t0 = time.time()
+    levels = P.build_psh(w.verts, w.tris, w.res, dilate=w.dilate, seed=w.psh_seed)
+    n_keys = sum(len(l.keys) for l in levels)
+    log(f"PSH built: {n_keys} keys in {time.time() - t0:.1f} s")
+    t0 = time.time()
+    feats = lambda l, lv: synth.feature_values(w.feature_seed, l, lv.keys, F=w.F)
+    R = P.Renderer(w.verts, w.tris, w.res, w.weights, feats, tables=("f32", "f16"), psh_levels=levels)
+    del levels
+    log(f"device model resident ({R.n_slots} slots/table) in {time.time() - t0:.1f} s")
+
+    out = {}
+    for prec, table in (("fp16", "f16"), ("fp32", "f32")):
+        r = run_frames(torch, R, w.cameras, prec, table, args.steps, args.warmup)
+        out[prec] = (r, summarize(r, W, H, args.steps, R.n_levels, table))
+        log(f"{prec}: {out[prec][1]['value']} Mrays/s, p50 {out[prec][1]['p50_ms']} ms, "
+            f"p99 {out[prec][1]['p99_ms']} ms, trace {out[prec][1]['trace_ms_avg']} ms, "
+            f"shade {out[prec][1]['shade_ms_avg']} ms")
+    mlp = {}
+    if not args.no_mlp:
+        for prec in ("fp16", "fp32"):
+            mlp[prec] = mlp_bench(torch, R, prec, args.mlp_rays)
+            log(f"mlp {prec}: {mlp[prec]}")
+    base = None
+    if not args.no_cpu_baseline:
+        log(f"timing the FP64 oracle on {args.cpu_sample} rays ...")
+        base = cpu_baseline(w, args.cpu_sample)
+        log(f"oracle: {base['value']} Mrays/s")
+
+    head = out["fp16"][1]
+    r16 = out["fp16"][0]
+    shade_avg_s = sum(r16["shade_ms"]) / args.steps / 1e3
+    bytes_launch = sum(r16["hits"]) / args.steps * requested_bytes_per_hit(R.n_levels, "f16")
+    achieved = bytes_launch / shade_avg_s / 1e9
+    line = {
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16",
+        "data": "synthetic",
+        "config": {"workload": w.name, "width": W, "height": H, "levels": R.n_levels, "res_max": max(w.res),
+                   "features": w.F, "mlp": "48-64-64-4", "cameras": len(w.cameras), "tables": "f16",
+                   "network": "fp16 MFMA, fp32 accumulate", "keys": n_keys},
+        "p50_ms": head["p50_ms"],
+        "p99_ms": head["p99_ms"],
+        "fp16": head,
+        "fp32": out["fp32"][1],
+        "fp16_over_fp32": round(head["value"] / out["fp32"][1]["value"], 3),
+        "roofline": {"kernel": "k_shade (PSH gather + trilinear + SH16 + MLP)", "bound": "hbm",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": load_traffic("k_shade_f16"),
+                     "per_unit": f"{requested_bytes_per_hit(R.n_levels, 'f16')} B requested per hit ray",
+                     "units_per_launch": round(sum(r16["hits"]) / args.steps, 1),
+                     "avg_launch_ms": round(shade_avg_s * 1e3, 4)},
+        "mlp": mlp or None,
+        "cpu_baseline": base,
+        "source": source_hash(),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -216,6 +216,14 @@ int64_t inrf_workspace_size(int64_t n_rays);
 inrf_status inrf_render(const inrf_model* m, int32_t precision, const inrf_camera* cam, float* rgba,
                         float* depth, int32_t* tri, void* ws, int64_t ws_bytes, void* stream);
 
+/* inrf_render with stage timing: events (host array of 3 hipEvent_t created
+ * by the caller; NULL entries are skipped) are recorded on `stream` before
+ * the trace, between the trace and the shading, and after the shading, so
+ * the caller can measure each stage with hipEventElapsedTime. */
+inrf_status inrf_render_profiled(const inrf_model* m, int32_t precision, const inrf_camera* cam, float* rgba,
+                                 float* depth, int32_t* tri, void* ws, int64_t ws_bytes, void* stream,
+                                 void* const* events);
+
 /* The same path on a batch of rays ("an indiscriminate range of rays with
  * depths", Sec. 1): ray_o, ray_d device float32 [n][3] (d need not be unit;
  * depth is then the ray parameter t); rgba device float32 [n][4]; depth and

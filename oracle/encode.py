@@ -73,15 +73,16 @@ def trilinear_encode(x, grid) -> np.ndarray:
     """Blend the eight corner features of each position: float64 [n, F]."""
     p, w = grid_cell(x, grid.res)
     n = len(p)
+    v = (p[:, None, :] + CORNERS[None]).reshape(-1, 3)          # [n*8, 3], corner-major per point
+    if isinstance(grid, FunctionGrid):
+        f = grid.lookup_many(v)
+    else:
+        f = np.array([grid(vi) for vi in v]).reshape(-1, grid.F)
+    f = f.reshape(n, 8, grid.F)
     out = np.zeros((n, grid.F))
-    for c in CORNERS:
+    for ci, c in enumerate(CORNERS):
         wc = np.prod(np.where(c[None, :] == 1, w, 1.0 - w), axis=1)
-        v = p + c[None, :]
-        if isinstance(grid, FunctionGrid):
-            f = grid.lookup_many(v)
-        else:
-            f = np.array([grid(vi) for vi in v]).reshape(n, grid.F)
-        out += wc[:, None] * f
+        out += wc[:, None] * f[:, ci]
     return out
 
 

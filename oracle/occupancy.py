@@ -110,7 +110,15 @@ def is_key(verts, tris, N: int, vertices, dilate: int = 1) -> np.ndarray:
     H = (hi - lo) * (S // 2)
     ok = (lo < hi).all(axis=1)
     out = np.zeros(len(v), bool)
-    for t in np.asarray(tris, np.int64).reshape(-1, 3):
+    if len(v) == 0:
+        return out
+    # only triangles whose bounding box meets the bounding box of all query
+    # boxes can meet one of them; the others are skipped unexamined
+    T = np.asarray(tris, np.int64).reshape(-1, 3)
+    bmin, bmax = (C - H).min(axis=0), (C + H).max(axis=0)
+    tmin, tmax = X[T].min(axis=1), X[T].max(axis=1)
+    near = np.all((tmin <= bmax) & (tmax >= bmin), axis=1)
+    for t in T[near]:
         out |= _sat_overlap(X[t], C, H) & ok
     return out
 

@@ -18,7 +18,8 @@ MAX_LEVELS, FEATURES, SH_DIM, HIDDEN, OUT = 32, 2, 16, 64, 4
 EXPORTED = [
     "inrf_last_error", "inrf_version", "inrf_psh_params_default", "inrf_build_psh", "inrf_build_psh_keys",
     "inrf_psh_levels", "inrf_psh_level", "inrf_psh_free", "inrf_build_bvh", "inrf_bvh_get_info",
-    "inrf_bvh_copy", "inrf_bvh_free", "inrf_workspace_size", "inrf_render", "inrf_forward", "inrf_trace",
+    "inrf_bvh_copy", "inrf_bvh_free", "inrf_workspace_size", "inrf_render", "inrf_render_profiled",
+    "inrf_forward", "inrf_trace",
     "inrf_encode", "inrf_mlp",
 ]
 
@@ -83,6 +84,8 @@ def _declare(lib):
         "inrf_workspace_size": (c_int64, [c_int64]),
         "inrf_render": (S, [POINTER(ModelDesc), c_int32, POINTER(CameraDesc), c_void_p, c_void_p, c_void_p,
                             c_void_p, c_int64, c_void_p]),
+        "inrf_render_profiled": (S, [POINTER(ModelDesc), c_int32, POINTER(CameraDesc), c_void_p, c_void_p,
+                                     c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
         "inrf_forward": (S, [POINTER(ModelDesc), c_int32, c_void_p, c_void_p, c_int64, c_void_p, c_void_p,
                              c_void_p, c_void_p, c_int64, c_void_p]),
         "inrf_trace": (S, [POINTER(ModelDesc), c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),

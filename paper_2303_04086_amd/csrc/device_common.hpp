@@ -74,10 +74,11 @@ struct TableRead<__half> {
 //   slot(v) = (v mod mbar + Phi[v mod rbar]) mod mbar, component-wise,
 // for the eight corners v = p + c of x's cell, blended trilinearly with
 // corner c = cx + 2cy + 4cz weighted prod_i (c_i ? w_i : 1 - w_i), summed in
-// ascending c.  Optionally reports the eight level-local linear slots.
+// ascending c.  Optionally writes the eight level-local linear slots to
+// slots_out[0..7] (global memory).
 template <class T>
 __device__ __forceinline__ float2 encode_level(const ModelC& m, const LevelC& L, float x, float y, float z,
-                                               int* slots_out) {
+                                               int32_t* __restrict__ slots_out) {
     int px, py, pz;
     float wx, wy, wz;
     cell_of(x, L.res, px, wx);

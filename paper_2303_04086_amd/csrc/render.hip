@@ -69,7 +69,12 @@ __device__ __forceinline__ RayPre ray_setup(float3 o, float3 d) {
     RayPre R;
     R.o = o;
     R.d = d;
-    R.inv = make_float3(1.f / d.x, 1.f / d.y, 1.f / d.z);
+    // slab reciprocals: a zero component becomes +-1e-30 so that a ray lying
+    // in a slab's boundary plane gives 0 * 1e30 = 0 instead of 0 * inf = NaN
+    const float tiny = 1e-30f;
+    R.inv = make_float3(1.f / (fabsf(d.x) < tiny ? copysignf(tiny, d.x) : d.x),
+                        1.f / (fabsf(d.y) < tiny ? copysignf(tiny, d.y) : d.y),
+                        1.f / (fabsf(d.z) < tiny ? copysignf(tiny, d.z) : d.z));
     const float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
     int kz = 0;
     if (ay > ax) kz = 1;
@@ -364,12 +369,9 @@ __global__ __launch_bounds__(kThreads) void k_encode(ModelC m, const float* __re
     if (i >= n) return;
     const float px = clamp01(x[3 * i]), py = clamp01(x[3 * i + 1]), pz = clamp01(x[3 * i + 2]);
     for (int l = 0; l < m.n_levels; ++l) {
-        int sl[8];
-        const float2 e = encode_level<TableT>(m, m.lv[l], px, py, pz, slots ? sl : nullptr);
+        const float2 e = encode_level<TableT>(m, m.lv[l], px, py, pz, slots ? slots + (i * m.n_levels + l) * 8 : nullptr);
         enc[i * 2 * m.n_levels + 2 * l] = e.x;
         enc[i * 2 * m.n_levels + 2 * l + 1] = e.y;
-        if (slots)
-            for (int c = 0; c < 8; ++c) slots[(i * m.n_levels + l) * 8 + c] = sl[c];
     }
 }
 
@@ -550,11 +552,17 @@ void check_precision(int32_t p) {
     require(p == INRF_PREC_FP32 || p == INRF_PREC_FP16 || p == INRF_PREC_BF16, "unknown precision");
 }
 
+void record(void* const* events, int i, hipStream_t s) {
+    if (events && events[i]) check_hip(hipEventRecord(reinterpret_cast<hipEvent_t>(events[i]), s), "hipEventRecord");
+}
+
 void run_path(const inrf_model* m, int32_t precision, const CamC* cam, const float* ray_o, const float* ray_d,
-              int64_t n, float* rgba, float* depth, int32_t* tri, void* ws, int64_t ws_bytes, void* stream) {
+              int64_t n, float* rgba, float* depth, int32_t* tri, void* ws, int64_t ws_bytes, void* stream,
+              void* const* events = nullptr) {
     check_precision(precision);
     const ModelC c = make_model(m, true, true);
     require(m->weights != nullptr, "weights must be set");
+    if (n == 0) return;
     require(rgba != nullptr, "rgba is NULL");
     require(ws != nullptr, "workspace is NULL");
     require((reinterpret_cast<uintptr_t>(ws) & 15) == 0 && (reinterpret_cast<uintptr_t>(rgba) & 15) == 0,
@@ -563,9 +571,9 @@ void run_path(const inrf_model* m, int32_t precision, const CamC* cam, const flo
         fail(INRF_E_SIZE, "workspace of " + std::to_string(ws_bytes) + " bytes < " +
                               std::to_string(inrf_workspace_size(n)) + " needed");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    if (n == 0) return;
     int32_t* counter = reinterpret_cast<int32_t*>(ws);
     HitRec* recs = reinterpret_cast<HitRec*>(reinterpret_cast<char*>(ws) + kWsHeader);
+    record(events, 0, s);
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, counter);
     launch_check("k_reset");
     TraceArgs a{ray_o, ray_d, n, rgba, depth, tri, recs, counter};
@@ -579,9 +587,31 @@ void run_path(const inrf_model* m, int32_t precision, const CamC* cam, const flo
                            none, a);
     }
     launch_check("k_trace");
+    record(events, 1, s);
     if (c.table_dtype == INRF_F32) launch_shade<float>(c, precision, recs, counter, rgba, s);
     else launch_shade<__half>(c, precision, recs, counter, rgba, s);
     launch_check("k_shade");
+    record(events, 2, s);
+}
+
+CamC make_camera(const inrf_camera* cam) {
+    require(cam != nullptr, "camera is NULL");
+    require(cam->width >= 1 && cam->height >= 1, "image size must be positive");
+    require(int64_t(cam->width) * cam->height <= (int64_t(1) << 31) - 1, "image too large");
+    CamC c;
+    for (int k = 0; k < 3; ++k) {
+        c.o[k] = cam->origin[k];
+        c.r[k] = cam->right[k];
+        c.u[k] = cam->up[k];
+        c.f[k] = cam->forward[k];
+    }
+    require(std::isfinite(cam->tan_half_fov_y) && cam->tan_half_fov_y > 0.f, "tan_half_fov_y must be > 0");
+    c.tan_y = cam->tan_half_fov_y;
+    c.tan_x = cam->tan_half_fov_y * float(cam->width) / float(cam->height);
+    c.W = cam->width;
+    c.H = cam->height;
+    c.tiles_x = (cam->width + kTile - 1) / kTile;
+    return c;
 }
 
 }  // namespace
@@ -599,24 +629,18 @@ int64_t inrf_workspace_size(int64_t n_rays) {
 inrf_status inrf_render(const inrf_model* m, int32_t precision, const inrf_camera* cam, float* rgba, float* depth,
                         int32_t* tri, void* ws, int64_t ws_bytes, void* stream) {
     return guarded("inrf_render", [&] {
-        require(cam != nullptr, "camera is NULL");
-        require(cam->width >= 1 && cam->height >= 1, "image size must be positive");
-        require(int64_t(cam->width) * cam->height <= (int64_t(1) << 31) - 1, "image too large");
-        dev::CamC c;
-        for (int k = 0; k < 3; ++k) {
-            c.o[k] = cam->origin[k];
-            c.r[k] = cam->right[k];
-            c.u[k] = cam->up[k];
-            c.f[k] = cam->forward[k];
-        }
-        require(std::isfinite(cam->tan_half_fov_y) && cam->tan_half_fov_y > 0.f, "tan_half_fov_y must be > 0");
-        c.tan_y = cam->tan_half_fov_y;
-        c.tan_x = cam->tan_half_fov_y * float(cam->width) / float(cam->height);
-        c.W = cam->width;
-        c.H = cam->height;
-        c.tiles_x = (cam->width + dev::kTile - 1) / dev::kTile;
-        run_path(m, precision, &c, nullptr, nullptr, int64_t(cam->width) * cam->height, rgba, depth, tri, ws,
-                 ws_bytes, stream);
+        const dev::CamC c = make_camera(cam);
+        run_path(m, precision, &c, nullptr, nullptr, int64_t(c.W) * c.H, rgba, depth, tri, ws, ws_bytes, stream);
+    });
+}
+
+inrf_status inrf_render_profiled(const inrf_model* m, int32_t precision, const inrf_camera* cam, float* rgba,
+                                 float* depth, int32_t* tri, void* ws, int64_t ws_bytes, void* stream,
+                                 void* const* events) {
+    return guarded("inrf_render_profiled", [&] {
+        const dev::CamC c = make_camera(cam);
+        run_path(m, precision, &c, nullptr, nullptr, int64_t(c.W) * c.H, rgba, depth, tri, ws, ws_bytes, stream,
+                 events);
     });
 }
 

@@ -202,17 +202,28 @@ class Renderer:
         return ctypes.c_void_p(s.cuda_stream)
 
     # -- calls -------------------------------------------------------------
-    def render(self, cam, precision="fp32", table="f32", rgba=None, depth=None, tri=None, stream=None):
+    def render(self, cam, precision="fp32", table="f32", rgba=None, depth=None, tri=None, stream=None,
+               events=None):
+        """Render one camera.  `events`: optional three recorded
+        torch.cuda.Event objects marking trace start, shading start and end."""
         torch = self.torch
         n = int(cam.width) * int(cam.height)
         if rgba is None:
             rgba = torch.empty((int(cam.height), int(cam.width), 4), dtype=torch.float32, device=self.device)
         ws = self.workspace(n)
         c = _camera_desc(cam)
-        L.check(L.lib().inrf_render(ctypes.byref(self.desc(table)), PRECISIONS[precision], ctypes.byref(c),
-                                    L.ptr(rgba), L.ptr(depth), L.ptr(tri), L.ptr(ws), ws.numel(),
-                                    self._stream(stream)))
+        args = (ctypes.byref(self.desc(table)), PRECISIONS[precision], ctypes.byref(c), L.ptr(rgba), L.ptr(depth),
+                L.ptr(tri), L.ptr(ws), ws.numel(), self._stream(stream))
+        if events is None:
+            L.check(L.lib().inrf_render(*args))
+        else:
+            arr = (ctypes.c_void_p * 3)(*[e.cuda_event if e is not None else 0 for e in events])
+            L.check(L.lib().inrf_render_profiled(*args, arr))
         return rgba
+
+    def hit_count(self) -> int:
+        """Hit rays of the last render/forward (reads the workspace counter)."""
+        return int(self._ws[:4].view(self.torch.int32).item())
 
     def forward(self, o, d, precision="fp32", table="f32", depth=None, tri=None, rgba=None, stream=None):
         torch = self.torch
