@@ -191,6 +191,8 @@ typedef struct inrf_model {
     const void* bvh_nodes;  /* device image from inrf_bvh_copy */
     const void* bvh_tris;   /* device image from inrf_bvh_copy */
     int64_t n_tris;         /* proxy triangles; 0 = empty proxy (every ray misses) */
+    int32_t bvh_depth;      /* inrf_bvh_info.depth of the image (sizes the traversal stack) */
+    int32_t pad1;
 } inrf_model;
 
 /* Pinhole camera (pose and intrinsics as a client sends them).  Pixel (i

@@ -16,14 +16,8 @@ ARCH = "gfx950"
 
 SOURCES = ["psh.cpp", "voxel.cpp", "bvh.cpp", "render.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", f"-I{INCLUDE}", f"-I{CSRC}"]
-# every HIP translation unit: gfx950 only, no packed FP32 instructions, and
-# matrix-core results kept in VGPRs: with accumulators in AGPRs the register
-# allocator placed some MFMA results in registers that partially overlap the
-# same instruction's accumulator input (e.g. a[2:5] <- mfma(.., a[4:7])), and
-# kernels compiled that way returned wrong sums on the device, while the same
-# source without such overlaps was exact.  The VGPR form emits none.
-HIP_FLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             "-mllvm", "-amdgpu-mfma-vgpr-form"]
+# every HIP translation unit: gfx950 only, no packed FP32 instructions
+HIP_FLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
 def _hipcc() -> str:

@@ -27,6 +27,8 @@ struct ModelC {
     const BvhNode* nodes;
     const BvhTri* tris;
     int64_t n_tris;
+    int32_t stack_depth;  // traversal stack entries per lane (BVH depth - 1, >= 1)
+    int32_t pad;
     LevelC lv[INRF_MAX_LEVELS];
 };
 
@@ -70,65 +72,108 @@ struct TableRead<__half> {
     }
 };
 
-// Perfect-spatial-hash encoding of one level (Sec. 4.1, Eq. 1):
+// Perfect-spatial-hash encoding (Sec. 4.1, Eq. 1):
 //   slot(v) = (v mod mbar + Phi[v mod rbar]) mod mbar, component-wise,
 // for the eight corners v = p + c of x's cell, blended trilinearly with
 // corner c = cx + 2cy + 4cz weighted prod_i (c_i ? w_i : 1 - w_i), summed in
-// ascending c.  Optionally writes the eight level-local linear slots to
-// slots_out[0..7] (global memory).
-template <class T>
-__device__ __forceinline__ float2 encode_level(const ModelC& m, const LevelC& L, float x, float y, float z,
-                                               int32_t* __restrict__ slots_out) {
-    int px, py, pz;
+// ascending c.
+//
+// The lookup of one level is two dependent memory round trips (offsets,
+// then features).  LevelQuery splits it so that a caller can issue the
+// offset loads of several levels before waiting on any of them.
+struct LevelQuery {
     float wx, wy, wz;
-    cell_of(x, L.res, px, wx);
-    cell_of(y, L.res, py, wy);
-    cell_of(z, L.res, pz, wz);
+    int hx, hy, hz;  // (p mod mbar) per axis
+    uint32_t o[8];   // packed offsets of the eight corners
+};
+
+// Cell, hash bases and the eight offset loads of one level.
+__device__ __forceinline__ void level_issue(const ModelC& m, const LevelC& L, float x, float y, float z,
+                                            LevelQuery& q) {
+    int px, py, pz;
+    cell_of(x, L.res, px, q.wx);
+    cell_of(y, L.res, py, q.wy);
+    cell_of(z, L.res, pz, q.wz);
     const int qx = mod_small(px, L.rbar, L.inv_rbar), qy = mod_small(py, L.rbar, L.inv_rbar),
               qz = mod_small(pz, L.rbar, L.inv_rbar);
-    const int hx = mod_small(px, L.mbar, L.inv_mbar), hy = mod_small(py, L.mbar, L.inv_mbar),
-              hz = mod_small(pz, L.mbar, L.inv_mbar);
+    q.hx = mod_small(px, L.mbar, L.inv_mbar);
+    q.hy = mod_small(py, L.mbar, L.inv_mbar);
+    q.hz = mod_small(pz, L.mbar, L.inv_mbar);
     const int qx1 = (qx + 1 == L.rbar) ? 0 : qx + 1, qy1 = (qy + 1 == L.rbar) ? 0 : qy + 1,
               qz1 = (qz + 1 == L.rbar) ? 0 : qz + 1;
     const uint32_t* phi = m.phi + L.phi_off;
-    uint32_t o[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         const int cx = (c & 1) ? qx1 : qx, cy = (c & 2) ? qy1 : qy, cz = (c & 4) ? qz1 : qz;
-        o[c] = phi[(cz * L.rbar + cy) * L.rbar + cx];
+        q.o[c] = phi[(cz * L.rbar + cy) * L.rbar + cx];
     }
-    float2 f[8];
-    int sl[8];
+}
+
+// Linear slot of corner c once its offset has arrived.
+__device__ __forceinline__ int level_slot(const LevelC& L, const LevelQuery& q, int c) {
+    int sx = q.hx + ((c & 1) ? 1 : 0) + int(q.o[c] & 1023u);
+    int sy = q.hy + ((c & 2) ? 1 : 0) + int((q.o[c] >> 10) & 1023u);
+    int sz = q.hz + ((c & 4) ? 1 : 0) + int((q.o[c] >> 20) & 1023u);
+    // (p + c) mod mbar <= mbar and an offset < mbar: one subtraction reduces
+    // the sum; the second step keeps a corrupt offset in bounds
+    if (sx >= L.mbar) sx -= L.mbar;
+    if (sy >= L.mbar) sy -= L.mbar;
+    if (sz >= L.mbar) sz -= L.mbar;
+    if (sx >= L.mbar) sx = mod_small(sx, L.mbar, L.inv_mbar);
+    if (sy >= L.mbar) sy = mod_small(sy, L.mbar, L.inv_mbar);
+    if (sz >= L.mbar) sz = mod_small(sz, L.mbar, L.inv_mbar);
+    return (sz * L.mbar + sy) * L.mbar + sx;
+}
+
+// Feature loads of the eight corners.
+template <class T>
+__device__ __forceinline__ void level_fetch(const ModelC& m, const LevelC& L, const LevelQuery& q, float2* f,
+                                            int32_t* __restrict__ slots_out) {
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-        int sx = hx + ((c & 1) ? 1 : 0), sy = hy + ((c & 2) ? 1 : 0), sz = hz + ((c & 4) ? 1 : 0);
-        sx += int(o[c] & 1023u);
-        sy += int((o[c] >> 10) & 1023u);
-        sz += int((o[c] >> 20) & 1023u);
-        // (p + c) mod mbar <= mbar and an offset < mbar: one subtraction
-        // reduces the sum; the second step keeps a corrupt offset in bounds
-        if (sx >= L.mbar) sx -= L.mbar;
-        if (sy >= L.mbar) sy -= L.mbar;
-        if (sz >= L.mbar) sz -= L.mbar;
-        if (sx >= L.mbar) sx = mod_small(sx, L.mbar, L.inv_mbar);
-        if (sy >= L.mbar) sy = mod_small(sy, L.mbar, L.inv_mbar);
-        if (sz >= L.mbar) sz = mod_small(sz, L.mbar, L.inv_mbar);
-        sl[c] = (sz * L.mbar + sy) * L.mbar + sx;
-        f[c] = TableRead<T>::get(m.table, L.slot_off + sl[c]);
+        const int s = level_slot(L, q, c);
+        f[c] = TableRead<T>::get(m.table, L.slot_off + s);
+        if (slots_out) slots_out[c] = s;
     }
-    if (slots_out) {
-#pragma unroll
-        for (int c = 0; c < 8; ++c) slots_out[c] = sl[c];
-    }
-    const float ux = 1.f - wx, uy = 1.f - wy, uz = 1.f - wz;
+}
+
+__device__ __forceinline__ float2 level_blend(const LevelQuery& q, const float2* f) {
+    const float ux = 1.f - q.wx, uy = 1.f - q.wy, uz = 1.f - q.wz;
     float2 e = make_float2(0.f, 0.f);
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-        const float wc = ((c & 1) ? wx : ux) * ((c & 2) ? wy : uy) * ((c & 4) ? wz : uz);
+        const float wc = ((c & 1) ? q.wx : ux) * ((c & 2) ? q.wy : uy) * ((c & 4) ? q.wz : uz);
         e.x += wc * f[c].x;
         e.y += wc * f[c].y;
     }
     return e;
+}
+
+// One level, optionally writing the eight level-local linear slots to
+// slots_out[0..7] (global memory).
+template <class T>
+__device__ __forceinline__ float2 encode_level(const ModelC& m, const LevelC& L, float x, float y, float z,
+                                               int32_t* __restrict__ slots_out) {
+    LevelQuery q;
+    level_issue(m, L, x, y, z, q);
+    float2 f[8];
+    level_fetch<T>(m, L, q, f, slots_out);
+    return level_blend(q, f);
+}
+
+// Two levels with their offset loads in flight together (x in [0,1]^3; a
+// lane with nothing to do passes a valid dummy point and drops the result).
+template <class T>
+__device__ __forceinline__ void encode_level_pair(const ModelC& m, const LevelC& La, const LevelC& Lb, float x,
+                                                  float y, float z, float2& ea, float2& eb) {
+    LevelQuery qa, qb;
+    level_issue(m, La, x, y, z, qa);
+    level_issue(m, Lb, x, y, z, qb);
+    float2 fa[8], fb[8];
+    level_fetch<T>(m, La, qa, fa, nullptr);
+    level_fetch<T>(m, Lb, qb, fb, nullptr);
+    ea = level_blend(qa, fa);
+    eb = level_blend(qb, fb);
 }
 
 // Real spherical harmonics of bands 0..3 of a unit vector, index l*l + l + m,

@@ -15,6 +15,7 @@
 // order in which waves append hits.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -159,7 +160,8 @@ __device__ __forceinline__ void leaf(const RayPre& R, const BvhTri* __restrict__
 }
 
 // Closest hit through the BVH; `stack` is this lane's column of an LDS stack
-// with stride kThreads (depth <= 32 guarantees at most 31 pushes).
+// with stride kThreads and m.stack_depth entries (a hierarchy of depth D
+// pushes at most D - 1 entries).
 __device__ void closest_hit(const ModelC& m, const RayPre& R, int* stack, float& best_t, int32_t& best_i) {
     best_t = INFINITY;
     best_i = -1;
@@ -184,7 +186,7 @@ __device__ void closest_hit(const ModelC& m, const RayPre& R, int* stack, float&
             leaf(R, m.tris, right, best_t, best_i);
             hr = false;
         }
-        if (hl && hr && sp < kBvhMaxDepth) {
+        if (hl && hr && sp < m.stack_depth) {
             const bool lfirst = tl <= tr;
             stack[(sp++) * kThreads] = lfirst ? right : left;
             node = lfirst ? left : right;
@@ -201,7 +203,7 @@ __device__ void closest_hit(const ModelC& m, const RayPre& R, int* stack, float&
 
 template <bool CAMERA>
 __global__ __launch_bounds__(kThreads) void k_trace(ModelC m, CamC cam, TraceArgs a) {
-    __shared__ int stack[32 * kThreads];
+    extern __shared__ int stack[];  // [m.stack_depth][kThreads]
     int64_t ray;
     bool valid;
     float3 o, d;
@@ -270,93 +272,79 @@ __global__ void k_reset(int32_t* counter) {
 
 // ------------------------------------------------------------- shading ----
 
-// FP32 network: one ray per lane, first layer streamed per level.
-template <class TableT>
-__global__ __launch_bounds__(kThreads) void k_shade_f32(ModelC m, const HitRec* __restrict__ recs,
-                                                        const int32_t* __restrict__ counter, float* __restrict__ rgba) {
-    extern __shared__ float lds_f[];
-    const int d_in = 2 * m.n_levels + INRF_SH_DIM;
-    f32_stage_weights(m.weights, d_in, lds_f);
+// Stages the weights (fragment order) and the level table into LDS; returns
+// the LDS level table.
+template <class P, int LPG>
+__device__ inline const LevelC* stage_model(const ModelC& m, typename Mfma<P>::vec* W) {
+    stage_weights<P>(m.weights, m.n_levels, LPG, W);
+    LevelC* lv = reinterpret_cast<LevelC*>(reinterpret_cast<char*>(W) + weight_bytes(LPG, Mfma<P>::V));
+    if (threadIdx.x == 0)
+        for (int l = 0; l < m.n_levels; ++l) lv[l] = m.lv[l];
     __syncthreads();
-    const float* L1 = lds_f;
-    const float* L2 = L1 + d_in * 64;
-    const float* L3 = L2 + 64 * 64;
-    const int n = *counter;
-    const int wave = int(threadIdx.x) / 64, lane = __lane_id();
-    for (int64_t base = (int64_t(blockIdx.x) * 4 + wave) * 64; base < n; base += int64_t(gridDim.x) * 256) {
-        const int64_t i = base + lane;
-        const bool act = i < n;
-        HitRec h;
-        if (act) h = recs[i];
-        else h = HitRec{0.5f, 0.5f, 0.5f, 0, 0.f, 0.f, 1.f, 0};
-        F32Acc a;
-        f32_zero(a);
-        for (int l = 0; l < m.n_levels; ++l) {
-            float2 e = make_float2(0.f, 0.f);
-            if (act) e = encode_level<TableT>(m, m.lv[l], h.x, h.y, h.z, nullptr);
-            f32_layer1_input(a, L1, 2 * l, e.x);
-            f32_layer1_input(a, L1, 2 * l + 1, e.y);
-        }
-        float sh[16];
-        sh16(h.dx, h.dy, h.dz, sh);
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            f32_layer1_input(a, L1, 2 * m.n_levels + k, sh[k]);
-            __builtin_amdgcn_sched_barrier(0);  // keep weight loads next to their use
-        }
-        const f32x4 o = f32_tail(a, L2, L3);
-        if (act)
-            reinterpret_cast<float4*>(rgba)[h.out] =
-                make_float4(sigmoidf(o[0]), sigmoidf(o[1]), sigmoidf(o[2]), sigmoidf(o[3]));
-    }
+    return lv;
 }
 
-// FP16/BF16 network: one ray per lane for the gather, inputs staged in LDS
-// in T, then four 16-ray blocks on 16x16x32 matrix cores.
-template <class TableT, class T, int C>
-__global__ __launch_bounds__(kThreads) void k_shade_lp(ModelC m, const HitRec* __restrict__ recs,
-                                                       const int32_t* __restrict__ counter, float* __restrict__ rgba) {
-    typedef typename LP<T>::vec V;
+__host__ __device__ constexpr size_t shade_lds_bytes(int lpg, int V) {
+    return size_t(weight_bytes(lpg, V)) + sizeof(LevelC) * INRF_MAX_LEVELS;
+}
+
+// This lane's first-layer values for hit point (x, y, z) and unit direction
+// d: features of levels g, g+4, ..., then SH values 4g..4g+3.  Levels are
+// fetched two at a time so their offset loads are in flight together; a lane
+// whose level lies beyond L looks up level 0 and drops the result.
+template <class TableT, int LPG>
+__device__ __forceinline__ void lane_features(const ModelC& m, const LevelC* lv, int g, float x, float y, float z,
+                                              float dx, float dy, float dz, float* in) {
+#pragma unroll
+    for (int j = 0; j < LPG; j += 2) {
+        const int la = g + 4 * j;
+        const bool va = la < m.n_levels;
+        if (j + 1 < LPG) {
+            const int lb = la + 4;
+            const bool vb = lb < m.n_levels;
+            float2 ea, eb;
+            encode_level_pair<TableT>(m, lv[va ? la : 0], lv[vb ? lb : 0], x, y, z, ea, eb);
+            in[2 * j] = va ? ea.x : 0.f;
+            in[2 * j + 1] = va ? ea.y : 0.f;
+            in[2 * j + 2] = vb ? eb.x : 0.f;
+            in[2 * j + 3] = vb ? eb.y : 0.f;
+            __builtin_amdgcn_sched_barrier(0);  // one pair of levels in flight at a time
+        } else {
+            const float2 ea = encode_level<TableT>(m, lv[va ? la : 0], x, y, z, nullptr);
+            in[2 * j] = va ? ea.x : 0.f;
+            in[2 * j + 1] = va ? ea.y : 0.f;
+        }
+    }
+    float sh[16];
+    sh16(dx, dy, dz, sh);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        in[2 * LPG + i] = g == 0 ? sh[i] : (g == 1 ? sh[4 + i] : (g == 2 ? sh[8 + i] : sh[12 + i]));
+}
+
+// Persistent waves over the packed hit list, 16 hits per wave step.
+template <class TableT, class P, int LPG>
+__global__ __launch_bounds__(kThreads) void k_shade(ModelC m, const HitRec* __restrict__ recs,
+                                                    const int32_t* __restrict__ counter, float* __restrict__ rgba) {
     extern __shared__ float4 lds_v[];
-    const int d_in = 2 * m.n_levels + INRF_SH_DIM;
-    V* W = reinterpret_cast<V*>(lds_v);
-    lp_stage_weights<T>(m.weights, d_in, W);
-    constexpr int stride = 32 * C + 8;  // elements per LDS row
-    T* X = reinterpret_cast<T*>(W + lp_lds_vecs(d_in));
-    const int wave = int(threadIdx.x) / 64, lane = __lane_id();
-    T* Xw = X + wave * 64 * stride;
-    for (int k = 2 * m.n_levels + INRF_SH_DIM; k < 32 * C; ++k) Xw[lane * stride + k] = LP<T>::cvt(0.f);
-    __syncthreads();
+    typedef typename Mfma<P>::vec Vec;
+    Vec* W = reinterpret_cast<Vec*>(lds_v);
+    const LevelC* lv = stage_model<P, LPG>(m, W);
     const int n = *counter;
-    for (int64_t base = (int64_t(blockIdx.x) * 4 + wave) * 64; base < n; base += int64_t(gridDim.x) * 256) {
-        const int64_t i = base + lane;
+    const int lane = __lane_id(), g = lane >> 4, r = lane & 15;
+    const int64_t n_waves = int64_t(gridDim.x) * (kThreads / 64);
+    for (int64_t blk = int64_t(blockIdx.x) * (kThreads / 64) + threadIdx.x / 64; blk * 16 < n; blk += n_waves) {
+        const int64_t i = blk * 16 + r;
         const bool act = i < n;
         HitRec h;
         if (act) h = recs[i];
-        else h = HitRec{0.5f, 0.5f, 0.5f, 0, 0.f, 0.f, 1.f, 0};
-        T* row = Xw + lane * stride;
-        for (int l = 0; l < m.n_levels; ++l) {
-            float2 e = make_float2(0.f, 0.f);
-            if (act) e = encode_level<TableT>(m, m.lv[l], h.x, h.y, h.z, nullptr);
-            row[2 * l] = LP<T>::cvt(e.x);
-            row[2 * l + 1] = LP<T>::cvt(e.y);
-        }
-        float sh[16];
-        sh16(h.dx, h.dy, h.dz, sh);
-#pragma unroll
-        for (int k = 0; k < 16; ++k) row[2 * m.n_levels + k] = LP<T>::cvt(sh[k]);
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        const int64_t nb = (n - base + 15) / 16;
-        for (int b = 0; b < 4 && b < nb; ++b) {
-            const f32x4 o = lp_block<T, C>(W, Xw + b * 16 * stride, stride);
-            const int src = b * 16 + (lane & 15);
-            const int out = __shfl(h.out, src);
-            if (lane < 16 && base + src < n)
-                reinterpret_cast<float4*>(rgba)[out] =
-                    make_float4(sigmoidf(o[0]), sigmoidf(o[1]), sigmoidf(o[2]), sigmoidf(o[3]));
-        }
-        __builtin_amdgcn_wave_barrier();
+        else h = HitRec{0.f, 0.f, 0.f, 0, 0.f, 0.f, 1.f, 0};
+        float in[lane_inputs(LPG)];
+        lane_features<TableT, LPG>(m, lv, g, h.x, h.y, h.z, h.dx, h.dy, h.dz, in);
+        const f32x4 o = mlp_block<P, LPG>(W, in);
+        if (g == 0 && act)
+            reinterpret_cast<float4*>(rgba)[h.out] =
+                make_float4(sigmoidf(o[0]), sigmoidf(o[1]), sigmoidf(o[2]), sigmoidf(o[3]));
     }
 }
 
@@ -375,60 +363,30 @@ __global__ __launch_bounds__(kThreads) void k_encode(ModelC m, const float* __re
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_mlp_f32(ModelC m, const float* __restrict__ in, int64_t n,
-                                                      float* __restrict__ rgba) {
-    extern __shared__ float lds_f[];
+// The network alone on caller inputs [n][d_in] in natural order.
+template <class P, int LPG>
+__global__ __launch_bounds__(kThreads) void k_mlp(ModelC m, const float* __restrict__ x, int64_t n,
+                                                  float* __restrict__ rgba) {
+    extern __shared__ float4 lds_v[];
+    typedef typename Mfma<P>::vec Vec;
+    Vec* W = reinterpret_cast<Vec*>(lds_v);
+    stage_model<P, LPG>(m, W);
     const int d_in = 2 * m.n_levels + INRF_SH_DIM;
-    f32_stage_weights(m.weights, d_in, lds_f);
-    __syncthreads();
-    const float* L1 = lds_f;
-    const float* L2 = L1 + d_in * 64;
-    const float* L3 = L2 + 64 * 64;
-    const int wave = int(threadIdx.x) / 64, lane = __lane_id();
-    for (int64_t base = (int64_t(blockIdx.x) * 4 + wave) * 64; base < n; base += int64_t(gridDim.x) * 256) {
-        const int64_t i = base + lane;
+    const int lane = __lane_id(), g = lane >> 4, r = lane & 15;
+    const int64_t n_waves = int64_t(gridDim.x) * (kThreads / 64);
+    for (int64_t blk = int64_t(blockIdx.x) * (kThreads / 64) + threadIdx.x / 64; blk * 16 < n; blk += n_waves) {
+        const int64_t i = blk * 16 + r;
         const bool act = i < n;
-        F32Acc a;
-        f32_zero(a);
-        for (int k = 0; k < d_in; ++k) f32_layer1_input(a, L1, k, act ? in[i * d_in + k] : 0.f);
-        const f32x4 o = f32_tail(a, L2, L3);
-        if (act)
+        float in[lane_inputs(LPG)];
+#pragma unroll
+        for (int v = 0; v < lane_inputs(LPG); ++v) {
+            const int k = input_index(g, v, LPG, m.n_levels);
+            in[v] = (act && k >= 0) ? x[i * d_in + k] : 0.f;
+        }
+        const f32x4 o = mlp_block<P, LPG>(W, in);
+        if (g == 0 && act)
             reinterpret_cast<float4*>(rgba)[i] =
                 make_float4(sigmoidf(o[0]), sigmoidf(o[1]), sigmoidf(o[2]), sigmoidf(o[3]));
-    }
-}
-
-template <class T, int C>
-__global__ __launch_bounds__(kThreads) void k_mlp_lp(ModelC m, const float* __restrict__ in, int64_t n,
-                                                     float* __restrict__ rgba) {
-    typedef typename LP<T>::vec V;
-    extern __shared__ float4 lds_v[];
-    const int d_in = 2 * m.n_levels + INRF_SH_DIM;
-    V* W = reinterpret_cast<V*>(lds_v);
-    lp_stage_weights<T>(m.weights, d_in, W);
-    constexpr int stride = 32 * C + 8;
-    T* X = reinterpret_cast<T*>(W + lp_lds_vecs(d_in));
-    const int wave = int(threadIdx.x) / 64, lane = __lane_id();
-    T* Xw = X + wave * 64 * stride;
-    __syncthreads();
-    for (int64_t base = (int64_t(blockIdx.x) * 4 + wave) * 64; base < n; base += int64_t(gridDim.x) * 256) {
-        // stage 64 rows (coalesced: consecutive lanes take consecutive elements)
-        for (int e = lane; e < 64 * 32 * C; e += 64) {
-            const int r = e / (32 * C), k = e % (32 * C);
-            const int64_t i = base + r;
-            Xw[r * stride + k] = LP<T>::cvt((i < n && k < d_in) ? in[i * d_in + k] : 0.f);
-        }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        const int64_t nb = (n - base + 15) / 16;
-        for (int b = 0; b < 4 && b < nb; ++b) {
-            const f32x4 o = lp_block<T, C>(W, Xw + b * 16 * stride, stride);
-            const int64_t i = base + b * 16 + lane;
-            if (lane < 16 && i < n)
-                reinterpret_cast<float4*>(rgba)[i] =
-                    make_float4(sigmoidf(o[0]), sigmoidf(o[1]), sigmoidf(o[2]), sigmoidf(o[3]));
-        }
-        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -471,10 +429,14 @@ ModelC make_model(const inrf_model* m, bool need_table, bool need_bvh) {
     c.nodes = reinterpret_cast<const BvhNode*>(m->bvh_nodes);
     c.tris = reinterpret_cast<const BvhTri*>(m->bvh_tris);
     c.n_tris = m->n_tris;
+    c.stack_depth = 1;
     if (need_table) require(m->phi && m->table, "phi and table must be set");
     if (need_bvh) {
         require(m->n_tris >= 0, "n_tris must be >= 0");
         require(m->n_tris == 0 || (m->bvh_nodes && m->bvh_tris), "bvh images must be set");
+        require(m->n_tris == 0 || (m->bvh_depth >= 1 && m->bvh_depth <= kBvhMaxDepth),
+                "bvh_depth must be the image's depth (1..32)");
+        c.stack_depth = std::max(1, m->bvh_depth - 1);
     }
     for (int l = 0; l < m->n_levels; ++l) {
         const inrf_level_desc& d = m->levels[l];
@@ -497,8 +459,6 @@ ModelC make_model(const inrf_model* m, bool need_table, bool need_bvh) {
 
 void launch_check(const char* what) { check_hip(hipGetLastError(), what); }
 
-int shade_grid() { return num_cus() * 2; }
-
 // Kernels whose dynamic LDS may exceed the default 64 KB window.
 template <class K>
 void allow_lds(K kernel, size_t bytes) {
@@ -508,44 +468,58 @@ void allow_lds(K kernel, size_t bytes) {
                   "hipFuncSetAttribute");
 }
 
-size_t shade_lds(int32_t precision, int d_in) {
-    if (precision == INRF_PREC_FP32) return size_t(f32_lds_floats(d_in)) * 4;
-    const int C = lp_chunks(d_in);
-    return size_t(lp_lds_vecs(d_in)) * 16 + size_t(4 * 64 * (32 * C + 8)) * 2;
+// Persistent grid: as many workgroups as the device keeps resident.
+template <class K>
+unsigned resident_grid(K kernel, size_t lds) {
+    int per_cu = 0;
+    check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, lds),
+              "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+    return unsigned(std::max(1, per_cu) * num_cus());
 }
+
+template <class TableT, class P, int LPG>
+void launch_shade_t(const ModelC& c, const HitRec* recs, const int32_t* counter, float* rgba, hipStream_t s) {
+    const size_t lds = shade_lds_bytes(LPG, Mfma<P>::V);
+    auto kern = k_shade<TableT, P, LPG>;
+    allow_lds(kern, lds);
+    hipLaunchKernelGGL(kern, dim3(resident_grid(kern, lds)), dim3(kThreads), lds, s, c, recs, counter, rgba);
+}
+
+template <class P, int LPG>
+void launch_mlp_t(const ModelC& c, const float* in, int64_t n, float* rgba, hipStream_t s) {
+    const size_t lds = shade_lds_bytes(LPG, Mfma<P>::V);
+    auto kern = k_mlp<P, LPG>;
+    allow_lds(kern, lds);
+    const int64_t blocks = (n + 63) / 64;
+    const unsigned grid = unsigned(std::min<int64_t>(blocks, resident_grid(kern, lds)));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, c, in, n, rgba);
+}
+
+// Levels per lane group (ceil(L / 4)) selects the instantiation.
+#define INRF_LPG_SWITCH(L, CALL)                              \
+    switch ((L + 3) / 4) {                                    \
+        case 1: CALL(1); break;                               \
+        case 2: CALL(2); break;                               \
+        case 3: CALL(3); break;                               \
+        case 4: CALL(4); break;                               \
+        case 5: CALL(5); break;                               \
+        case 6: CALL(6); break;                               \
+        case 7: CALL(7); break;                               \
+        case 8: CALL(8); break;                               \
+        default: fail(INRF_E_UNSUPPORTED, "level count");     \
+    }
 
 template <class TableT>
 void launch_shade(const ModelC& c, int32_t precision, const HitRec* recs, const int32_t* counter, float* rgba,
                   hipStream_t s) {
-    const int d_in = 2 * c.n_levels + INRF_SH_DIM;
-    const size_t lds = shade_lds(precision, d_in);
-    const int C = lp_chunks(d_in);
-    const dim3 grid(shade_grid()), block(kThreads);
-    if (precision == INRF_PREC_FP32) {
-        hipLaunchKernelGGL(k_shade_f32<TableT>, grid, block, lds, s, c, recs, counter, rgba);
-        return;
-    }
-#define INRF_LP_CASE(TT, CC)                                                                     \
-    case CC:                                                                                     \
-        allow_lds(k_shade_lp<TableT, TT, CC>, lds);                                              \
-        hipLaunchKernelGGL((k_shade_lp<TableT, TT, CC>), grid, block, lds, s, c, recs, counter, rgba); \
-        break;
-    if (precision == INRF_PREC_FP16) {
-        switch (C) {
-            INRF_LP_CASE(_Float16, 1)
-            INRF_LP_CASE(_Float16, 2)
-            INRF_LP_CASE(_Float16, 3)
-            default: fail(INRF_E_UNSUPPORTED, "input width");
-        }
-    } else {
-        switch (C) {
-            INRF_LP_CASE(__bf16, 1)
-            INRF_LP_CASE(__bf16, 2)
-            INRF_LP_CASE(__bf16, 3)
-            default: fail(INRF_E_UNSUPPORTED, "input width");
-        }
-    }
-#undef INRF_LP_CASE
+#define INRF_SHADE(LPG)                                                                   \
+    do {                                                                                 \
+        if (precision == INRF_PREC_FP32) launch_shade_t<TableT, float, LPG>(c, recs, counter, rgba, s);      \
+        else if (precision == INRF_PREC_FP16) launch_shade_t<TableT, _Float16, LPG>(c, recs, counter, rgba, s); \
+        else launch_shade_t<TableT, __bf16, LPG>(c, recs, counter, rgba, s);             \
+    } while (0)
+    INRF_LPG_SWITCH(c.n_levels, INRF_SHADE)
+#undef INRF_SHADE
 }
 
 void check_precision(int32_t p) {
@@ -577,14 +551,15 @@ void run_path(const inrf_model* m, int32_t precision, const CamC* cam, const flo
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, counter);
     launch_check("k_reset");
     TraceArgs a{ray_o, ray_d, n, rgba, depth, tri, recs, counter};
+    const size_t stack_bytes = size_t(c.stack_depth) * kThreads * sizeof(int);
     if (cam) {
         const int tiles = cam->tiles_x * ((cam->H + kTile - 1) / kTile);
-        hipLaunchKernelGGL(k_trace<true>, dim3(tiles), dim3(kThreads), 0, s, c, *cam, a);
+        hipLaunchKernelGGL(k_trace<true>, dim3(tiles), dim3(kThreads), stack_bytes, s, c, *cam, a);
     } else {
         CamC none;
         std::memset(&none, 0, sizeof(none));
-        hipLaunchKernelGGL(k_trace<false>, dim3(unsigned((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, c,
-                           none, a);
+        hipLaunchKernelGGL(k_trace<false>, dim3(unsigned((n + kThreads - 1) / kThreads)), dim3(kThreads),
+                           stack_bytes, s, c, none, a);
     }
     launch_check("k_trace");
     record(events, 1, s);
@@ -663,8 +638,9 @@ inrf_status inrf_trace(const inrf_model* m, const float* ray_o, const float* ray
         dev::TraceArgs a{ray_o, ray_d, n, nullptr, t, tri, nullptr, nullptr};
         dev::CamC none;
         std::memset(&none, 0, sizeof(none));
+        const size_t stack_bytes = size_t(c.stack_depth) * dev::kThreads * sizeof(int);
         hipLaunchKernelGGL(dev::k_trace<false>, dim3(unsigned((n + dev::kThreads - 1) / dev::kThreads)),
-                           dim3(dev::kThreads), 0, reinterpret_cast<hipStream_t>(stream), c, none, a);
+                           dim3(dev::kThreads), stack_bytes, reinterpret_cast<hipStream_t>(stream), c, none, a);
         launch_check("k_trace");
     });
 }
@@ -696,25 +672,15 @@ inrf_status inrf_mlp(const inrf_model* m, int32_t precision, const float* in, in
         std::memset(&c, 0, sizeof(c));
         c.n_levels = m->n_levels;
         c.weights = m->weights;
-        const int d_in = 2 * c.n_levels + INRF_SH_DIM;
-        const size_t lds = shade_lds(precision, d_in);
-        const int64_t waves = (n + 63) / 64;
-        const unsigned grid = unsigned(std::min<int64_t>((waves + 3) / 4, int64_t(num_cus()) * 4));
         hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-        const int C = dev::lp_chunks(d_in);
-        if (precision == INRF_PREC_FP32) {
-            hipLaunchKernelGGL(dev::k_mlp_f32, dim3(grid), dim3(dev::kThreads), lds, s, c, in, n, rgba);
-        } else if (precision == INRF_PREC_FP16) {
-            allow_lds(dev::k_mlp_lp<_Float16, 3>, lds);
-            if (C == 1) hipLaunchKernelGGL((dev::k_mlp_lp<_Float16, 1>), dim3(grid), dim3(dev::kThreads), lds, s, c, in, n, rgba);
-            else if (C == 2) hipLaunchKernelGGL((dev::k_mlp_lp<_Float16, 2>), dim3(grid), dim3(dev::kThreads), lds, s, c, in, n, rgba);
-            else hipLaunchKernelGGL((dev::k_mlp_lp<_Float16, 3>), dim3(grid), dim3(dev::kThreads), lds, s, c, in, n, rgba);
-        } else {
-            allow_lds(dev::k_mlp_lp<__bf16, 3>, lds);
-            if (C == 1) hipLaunchKernelGGL((dev::k_mlp_lp<__bf16, 1>), dim3(grid), dim3(dev::kThreads), lds, s, c, in, n, rgba);
-            else if (C == 2) hipLaunchKernelGGL((dev::k_mlp_lp<__bf16, 2>), dim3(grid), dim3(dev::kThreads), lds, s, c, in, n, rgba);
-            else hipLaunchKernelGGL((dev::k_mlp_lp<__bf16, 3>), dim3(grid), dim3(dev::kThreads), lds, s, c, in, n, rgba);
-        }
+#define INRF_MLP(LPG)                                                             \
+    do {                                                                         \
+        if (precision == INRF_PREC_FP32) launch_mlp_t<float, LPG>(c, in, n, rgba, s);        \
+        else if (precision == INRF_PREC_FP16) launch_mlp_t<_Float16, LPG>(c, in, n, rgba, s); \
+        else launch_mlp_t<__bf16, LPG>(c, in, n, rgba, s);                       \
+    } while (0)
+        INRF_LPG_SWITCH(c.n_levels, INRF_MLP)
+#undef INRF_MLP
         launch_check("k_mlp");
     });
 }

@@ -188,6 +188,7 @@ class Renderer:
             m.bvh_nodes = self.bvh_nodes.data_ptr()
             m.bvh_tris = self.bvh_tris.data_ptr()
             m.n_tris = self.n_tris
+            m.bvh_depth = self.bvh.depth
             self._descs[table] = m
         return self._descs[table]
 
