@@ -148,16 +148,18 @@ void inrf_psh_free(inrf_psh* psh);
 typedef struct inrf_bvh inrf_bvh; /* opaque host object */
 
 typedef struct inrf_bvh_info {
-    int64_t n_nodes;    /* binary nodes */
+    int64_t n_nodes;    /* four-wide nodes */
     int64_t node_bytes; /* size of the node image */
     int64_t tri_bytes;  /* size of the triangle image */
-    int32_t depth;      /* deepest leaf (root = 1), at most 32 */
+    int32_t depth;      /* deepest leaf (root = 1) */
     int32_t max_leaf;   /* triangles per leaf, at most 4 */
+    int32_t stack;      /* traversal stack entries a ray can need (1..64) */
+    int32_t pad;
 } inrf_bvh_info;
 
-/* Binned-SAH bounding volume hierarchy over the proxy (the paper queries a
- * geometry proxy per ray, abstract and Sec. 1; this is its acceleration
- * structure).  Same vertex/triangle arguments as inrf_build_psh, except that
+/* Bounding volume hierarchy over the proxy (the paper queries a geometry
+ * proxy per ray, abstract and Sec. 1; this is its acceleration structure):
+ * binned SAH, then collapsed to four-wide nodes.  Same vertex/triangle arguments as inrf_build_psh, except that
  * coordinates need not lie on the lattice (they must be finite). */
 inrf_status inrf_build_bvh(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
                            inrf_bvh** out);
@@ -191,7 +193,7 @@ typedef struct inrf_model {
     const void* bvh_nodes;  /* device image from inrf_bvh_copy */
     const void* bvh_tris;   /* device image from inrf_bvh_copy */
     int64_t n_tris;         /* proxy triangles; 0 = empty proxy (every ray misses) */
-    int32_t bvh_depth;      /* inrf_bvh_info.depth of the image (sizes the traversal stack) */
+    int32_t bvh_stack;      /* inrf_bvh_info.stack of the image (sizes the traversal stack) */
     int32_t pad1;
 } inrf_model;
 

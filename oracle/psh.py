@@ -11,8 +11,9 @@ neighbouring points to neighbouring slots (Sec. 4.1 and the PSH figure) but
 does not spell it out; the deterministic greedy adopted here is:
 
   sizes   mbar = smallest integer with load_pct * mbar**3 >= 100 * n (the
-          table is at most load_pct % full; default 80);
-          rbar = smallest integer with bucket_keys * rbar**3 >= n (about
+          table is at most load_pct % full; default 80) and 1024 * mbar >= N + 1
+          (which keeps rbar <= 1024);
+          rbar = smallest integer >= 2 with bucket_keys * rbar**3 >= n (about
           bucket_keys keys per offset entry; default 2), then increased until
           gcd(mbar, rbar) = 1 and mbar * rbar >= N + 1.  Keys sharing a bucket
           then differ modulo mbar (Chinese remainder theorem), so any offset
@@ -161,8 +162,8 @@ def build_psh_level(keys, N: int, seed: int = 1, load_pct: int = 80, bucket_keys
     """Build Phi and the slot of each key; keys int [n, 3] in canonical order."""
     keys = np.asarray(keys, np.int64).reshape(-1, 3)
     n = len(keys)
-    mbar = _icbrt_ceil(100 * max(n, 1), load_pct)
-    rbar = _fix_rbar(_icbrt_ceil(max(n, 1), bucket_keys), mbar, N)
+    mbar = max(_icbrt_ceil(100 * max(n, 1), load_pct), -(-(N + 1) // 1024))
+    rbar = _fix_rbar(max(2, _icbrt_ceil(max(n, 1), bucket_keys)), mbar, N)
     while True:
         for _ in range(max_restarts + 1):
             if mbar > 1024:

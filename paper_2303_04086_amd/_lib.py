@@ -42,7 +42,7 @@ class PshLevelInfo(ctypes.Structure):
 
 class BvhInfo(ctypes.Structure):
     _fields_ = [("n_nodes", c_int64), ("node_bytes", c_int64), ("tri_bytes", c_int64), ("depth", c_int32),
-                ("max_leaf", c_int32)]
+                ("max_leaf", c_int32), ("stack", c_int32), ("pad", c_int32)]
 
 
 class LevelDesc(ctypes.Structure):
@@ -53,7 +53,7 @@ class LevelDesc(ctypes.Structure):
 class ModelDesc(ctypes.Structure):
     _fields_ = [("n_levels", c_int32), ("table_dtype", c_int32), ("levels", LevelDesc * MAX_LEVELS),
                 ("phi", c_void_p), ("table", c_void_p), ("weights", c_void_p), ("bvh_nodes", c_void_p),
-                ("bvh_tris", c_void_p), ("n_tris", c_int64), ("bvh_depth", c_int32), ("pad1", c_int32)]
+                ("bvh_tris", c_void_p), ("n_tris", c_int64), ("bvh_stack", c_int32), ("pad1", c_int32)]
 
 
 class CameraDesc(ctypes.Structure):

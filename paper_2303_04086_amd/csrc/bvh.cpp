@@ -34,13 +34,20 @@ struct Box {
     }
 };
 
+// Binary node during the build: both children's boxes and references
+// (same reference encoding as the four-wide image).
+struct BinNode {
+    Box lb, rb;
+    int32_t left, right;
+};
+
 struct Builder {
     const float* V;
     const int32_t* T;
     std::vector<Box> tb;         // triangle boxes
     std::vector<float> cen;      // centroids [n][3]
     std::vector<int32_t> order;  // triangle permutation
-    std::vector<BvhNode> nodes;
+    std::vector<BinNode> nodes;
     int depth = 0;
     bool median_only = false;
 
@@ -135,13 +142,9 @@ struct Builder {
         const Box lb = bounds(b, m), rb = bounds(m, e);
         const int32_t l = build(b, m, d + 1);
         const int32_t r = build(m, e, d + 1);
-        BvhNode& nd = nodes[size_t(id)];
-        for (int k = 0; k < 3; ++k) {
-            nd.lmin[k] = lb.lo[k];
-            nd.lmax[k] = lb.hi[k];
-            nd.rmin[k] = rb.lo[k];
-            nd.rmax[k] = rb.hi[k];
-        }
+        BinNode& nd = nodes[size_t(id)];
+        nd.lb = lb;
+        nd.rb = rb;
         nd.left = l;
         nd.right = r;
         return id;
@@ -153,21 +156,83 @@ struct Builder {
         nodes.clear();
         depth = 0;
         if (nt <= kBvhMaxLeaf) {
-            BvhNode root{};
-            const Box bx = bounds(0, int32_t(nt));
-            for (int k = 0; k < 3; ++k) {
-                root.lmin[k] = bx.lo[k];
-                root.lmax[k] = bx.hi[k];
-                root.rmin[k] = INFINITY;
-                root.rmax[k] = -INFINITY;
-            }
-            root.left = bvh_leaf_ref(0, int32_t(nt));
-            root.right = bvh_leaf_ref(0, 0);
+            BinNode root;
+            root.lb = bounds(0, int32_t(nt));
+            root.left = nt > 0 ? bvh_leaf_ref(0, int32_t(nt)) : kBvhEmpty;
+            root.right = kBvhEmpty;
             nodes.push_back(root);
             depth = 2;
             return;
         }
         build(0, int32_t(nt), 1);  // depth = level of the deepest leaf, root = 1
+    }
+};
+
+// Collapses the binary hierarchy into four-wide nodes: a node's slots start
+// as its two children and the interior slot with the largest box area is
+// replaced by its own two children until four slots are used or none is
+// interior.  Also returns the traversal stack entries a ray can need: a node
+// with k interior children defers up to k - 1 of them.
+struct Collapser {
+    const std::vector<BinNode>& bin;
+    std::vector<BvhNode> out;
+    int32_t depth = 0;
+
+    struct Slot {
+        int32_t ref;
+        Box box;
+    };
+
+    // returns the stack need of the subtree rooted at the new node
+    int32_t collapse(int32_t bin_id, int32_t level, int32_t* out_id) {
+        depth = std::max(depth, level);
+        Slot s[4];
+        int n = 0;
+        const BinNode& b = bin[size_t(bin_id)];
+        if (b.left != kBvhEmpty) s[n++] = Slot{b.left, b.lb};
+        if (b.right != kBvhEmpty) s[n++] = Slot{b.right, b.rb};
+        while (n < 4) {
+            int pick = -1;
+            double best = -1.0;
+            for (int i = 0; i < n; ++i)
+                if (s[i].ref >= 0 && s[i].box.area() > best) {
+                    best = s[i].box.area();
+                    pick = i;
+                }
+            if (pick < 0) break;
+            const BinNode& c = bin[size_t(s[pick].ref)];
+            s[pick] = Slot{c.left, c.lb};
+            if (c.right != kBvhEmpty) s[n++] = Slot{c.right, c.rb};
+        }
+        const int32_t id = int32_t(out.size());
+        out.emplace_back();
+        *out_id = id;
+        int32_t child_ref[4] = {kBvhEmpty, kBvhEmpty, kBvhEmpty, kBvhEmpty};
+        int interior = 0;
+        int32_t sub = 0;
+        for (int i = 0; i < n; ++i) {
+            if (s[i].ref >= 0) {
+                int32_t cid;
+                sub = std::max(sub, collapse(s[i].ref, level + 1, &cid));
+                child_ref[i] = cid;
+                ++interior;
+            } else {
+                child_ref[i] = s[i].ref;
+            }
+        }
+        BvhNode& nd = out[size_t(id)];
+        for (int i = 0; i < 4; ++i) {
+            const Box bx = i < n ? s[i].box : Box();
+            nd.lox[i] = bx.lo[0];
+            nd.loy[i] = bx.lo[1];
+            nd.loz[i] = bx.lo[2];
+            nd.hix[i] = bx.hi[0];
+            nd.hiy[i] = bx.hi[1];
+            nd.hiz[i] = bx.hi[2];
+            nd.child[i] = child_ref[i];
+            nd.pad[i] = 0;
+        }
+        return std::max(0, interior - 1) + sub;
     }
 };
 
@@ -178,6 +243,7 @@ struct inrf_bvh {
     std::vector<inrf::BvhNode> nodes;
     std::vector<inrf::BvhTri> tris;
     int32_t depth = 0;
+    int32_t stack = 0;
 };
 
 using namespace inrf;
@@ -212,9 +278,14 @@ inrf_status inrf_build_bvh(const float* verts, int64_t n_verts, const int32_t* t
             B.run(n_tris);
         }
         if (B.depth > kBvhMaxDepth) fail(INRF_E_BUILD, "hierarchy deeper than 32 levels");
+        Collapser C{B.nodes, {}, 0};
+        int32_t root = 0;
+        const int32_t stack = C.collapse(0, 1, &root);
+        if (stack > kBvhMaxStack) fail(INRF_E_BUILD, "traversal would need more than 64 stack entries");
         auto* obj = new inrf_bvh();
-        obj->nodes = std::move(B.nodes);
-        obj->depth = B.depth;
+        obj->nodes = std::move(C.out);
+        obj->depth = C.depth + 1;  // leaves sit below the deepest node
+        obj->stack = std::max(1, stack);
         obj->tris.resize(size_t(n_tris));
         for (int64_t i = 0; i < n_tris; ++i) {
             const int32_t t = B.order[size_t(i)];
@@ -239,6 +310,8 @@ inrf_status inrf_bvh_get_info(const inrf_bvh* bvh, inrf_bvh_info* info) {
         info->tri_bytes = int64_t(bvh->tris.size() * sizeof(BvhTri));
         info->depth = bvh->depth;
         info->max_leaf = kBvhMaxLeaf;
+        info->stack = bvh->stack;
+        info->pad = 0;
     });
 }
 

@@ -1,12 +1,14 @@
 // Memory images of the proxy BVH, shared by the host builder and the
 // traversal kernels.
 //
-// Node (64 bytes, one per interior split): the boxes of both children, so a
-// visit tests two boxes with one 64-byte read.  A child reference >= 0 is a
-// node index; a negative reference r encodes a leaf, ~r = first << 3 | count
-// (count 0..4 triangles starting at `first` in the triangle image).  Node 0 is
-// the root; a proxy of <= 4 triangles is a root with one leaf and one empty
-// leaf.  Boxes are the exact FP32 min/max of the triangles below.
+// Node (128 bytes, four children): the children's boxes as structure of
+// arrays (min x of children 0..3, min y, min z, max x, max y, max z), then
+// four child references.  A reference >= 0 is a node index; a negative
+// reference r encodes a leaf, ~r = first << 3 | count (1..4 triangles starting
+// at `first` in the triangle image); -1 marks an unused slot.  Node 0 is the
+// root.  Boxes are the exact FP32 min/max of the triangles below.  The image
+// is built as a binary SAH hierarchy and then collapsed to four-wide nodes,
+// which halves the dependent node fetches of a traversal.
 //
 // Triangle (48 bytes, leaf order): v0.xyz + original index (as int bits),
 // v1.xyz + 0, v2.xyz + 0.
@@ -17,14 +19,14 @@
 namespace inrf {
 
 struct alignas(16) BvhNode {
-    float lmin[3];
-    float lmax[3];
-    float rmin[3];
-    float rmax[3];
-    int32_t left, right;
-    int32_t pad[2];
+    float lox[4], loy[4], loz[4];
+    float hix[4], hiy[4], hiz[4];
+    int32_t child[4];
+    int32_t pad[4];
 };
-static_assert(sizeof(BvhNode) == 64, "node image is 64 bytes");
+static_assert(sizeof(BvhNode) == 128, "node image is 128 bytes");
+
+constexpr int32_t kBvhEmpty = -1;
 
 struct alignas(16) BvhTri {
     float v0[3];
@@ -37,7 +39,8 @@ struct alignas(16) BvhTri {
 static_assert(sizeof(BvhTri) == 48, "triangle image is 48 bytes");
 
 constexpr int kBvhMaxLeaf = 4;
-constexpr int kBvhMaxDepth = 32;
+constexpr int kBvhMaxDepth = 32;   // binary hierarchy before collapsing
+constexpr int kBvhMaxStack = 64;   // traversal stack entries a hierarchy may need
 
 inline int32_t bvh_leaf_ref(int32_t first, int32_t count) { return ~((first << 3) | count); }
 

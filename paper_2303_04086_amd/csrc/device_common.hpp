@@ -15,7 +15,7 @@ namespace dev {
 
 struct LevelC {
     int32_t res, mbar, rbar, pad;
-    float inv_mbar, inv_rbar;
+    uint32_t magic_mbar, magic_rbar;  // ceil(2^32 / m): p mod m = p - m * umulhi(p, magic)
     int64_t phi_off, slot_off;
 };
 
@@ -27,20 +27,21 @@ struct ModelC {
     const BvhNode* nodes;
     const BvhTri* tris;
     int64_t n_tris;
-    int32_t stack_depth;  // traversal stack entries per lane (BVH depth - 1, >= 1)
+    int32_t stack_depth;  // traversal stack entries per lane (the image's bound, >= 1)
     int32_t pad;
     LevelC lv[INRF_MAX_LEVELS];
 };
 
-// a mod m for 0 <= a < 2^14, 1 <= m <= 2^14, via a float reciprocal and one
-// correction step (the quotient estimate is off by at most one).
-__device__ __forceinline__ int mod_small(int a, int m, float inv_m) {
-    const int d = int(float(a) * inv_m);
-    int r = a - d * m;
-    if (r < 0) r += m;
-    else if (r >= m) r -= m;
-    return r;
+// a mod m for 0 <= a < 2^14 and 1 <= m <= 2^10 with magic = ceil(2^32 / m):
+// magic * m - 2^32 = e < m, so a * magic / 2^32 exceeds a / m by less than
+// a * e / (m 2^32) < 1 / m, which never crosses the next integer -- the
+// quotient umulhi(a, magic) is exact.
+__device__ __forceinline__ int mod_small(int a, int m, uint32_t magic) {
+    return a - m * int(__umulhi(uint32_t(a), magic));
 }
+
+// (a >= m ? a - m : a) for 0 <= a < 2m, as an unsigned minimum.
+__device__ __forceinline__ int wrap_once(int a, int m) { return int(min(uint32_t(a), uint32_t(a - m))); }
 
 // Cell of x (already in [0,1]) on a grid of N cells: p = floor of the exact
 // product N*x, clamped to N-1, and w = N*x - p rounded once (Sec. 4.1: scale
@@ -94,11 +95,11 @@ __device__ __forceinline__ void level_issue(const ModelC& m, const LevelC& L, fl
     cell_of(x, L.res, px, q.wx);
     cell_of(y, L.res, py, q.wy);
     cell_of(z, L.res, pz, q.wz);
-    const int qx = mod_small(px, L.rbar, L.inv_rbar), qy = mod_small(py, L.rbar, L.inv_rbar),
-              qz = mod_small(pz, L.rbar, L.inv_rbar);
-    q.hx = mod_small(px, L.mbar, L.inv_mbar);
-    q.hy = mod_small(py, L.mbar, L.inv_mbar);
-    q.hz = mod_small(pz, L.mbar, L.inv_mbar);
+    const int qx = mod_small(px, L.rbar, L.magic_rbar), qy = mod_small(py, L.rbar, L.magic_rbar),
+              qz = mod_small(pz, L.rbar, L.magic_rbar);
+    q.hx = mod_small(px, L.mbar, L.magic_mbar);
+    q.hy = mod_small(py, L.mbar, L.magic_mbar);
+    q.hz = mod_small(pz, L.mbar, L.magic_mbar);
     const int qx1 = (qx + 1 == L.rbar) ? 0 : qx + 1, qy1 = (qy + 1 == L.rbar) ? 0 : qy + 1,
               qz1 = (qz + 1 == L.rbar) ? 0 : qz + 1;
     const uint32_t* phi = m.phi + L.phi_off;
@@ -109,20 +110,15 @@ __device__ __forceinline__ void level_issue(const ModelC& m, const LevelC& L, fl
     }
 }
 
-// Linear slot of corner c once its offset has arrived.
+// Linear slot of corner c once its offset has arrived.  (p + c) mod mbar is
+// at most mbar and a valid offset is below mbar, so one wrap reduces each
+// component; the final clamp keeps even a corrupt offset inside the level.
 __device__ __forceinline__ int level_slot(const LevelC& L, const LevelQuery& q, int c) {
-    int sx = q.hx + ((c & 1) ? 1 : 0) + int(q.o[c] & 1023u);
-    int sy = q.hy + ((c & 2) ? 1 : 0) + int((q.o[c] >> 10) & 1023u);
-    int sz = q.hz + ((c & 4) ? 1 : 0) + int((q.o[c] >> 20) & 1023u);
-    // (p + c) mod mbar <= mbar and an offset < mbar: one subtraction reduces
-    // the sum; the second step keeps a corrupt offset in bounds
-    if (sx >= L.mbar) sx -= L.mbar;
-    if (sy >= L.mbar) sy -= L.mbar;
-    if (sz >= L.mbar) sz -= L.mbar;
-    if (sx >= L.mbar) sx = mod_small(sx, L.mbar, L.inv_mbar);
-    if (sy >= L.mbar) sy = mod_small(sy, L.mbar, L.inv_mbar);
-    if (sz >= L.mbar) sz = mod_small(sz, L.mbar, L.inv_mbar);
-    return (sz * L.mbar + sy) * L.mbar + sx;
+    const int sx = wrap_once(q.hx + ((c & 1) ? 1 : 0) + int(q.o[c] & 1023u), L.mbar);
+    const int sy = wrap_once(q.hy + ((c & 2) ? 1 : 0) + int((q.o[c] >> 10) & 1023u), L.mbar);
+    const int sz = wrap_once(q.hz + ((c & 4) ? 1 : 0) + int((q.o[c] >> 20) & 1023u), L.mbar);
+    const int s = (sz * L.mbar + sy) * L.mbar + sx;
+    return min(s, L.mbar * L.mbar * L.mbar - 1);
 }
 
 // Feature loads of the eight corners.

@@ -7,9 +7,10 @@
 // paper's offsets come from a heuristic that prefers mapping neighbouring
 // points to neighbouring slots; this is the deterministic greedy used here:
 //
-//   sizes    mbar: smallest with load_pct*mbar^3 >= 100*n.
-//            rbar: smallest with bucket_keys*rbar^3 >= n, then grown until
-//            gcd(mbar, rbar) = 1 and mbar*rbar >= N+1; by the Chinese
+//   sizes    mbar: smallest with load_pct*mbar^3 >= 100*n and
+//            1024*mbar >= N+1.
+//            rbar: smallest >= 2 with bucket_keys*rbar^3 >= n, then grown
+//            until gcd(mbar, rbar) = 1 and mbar*rbar >= N+1; by the Chinese
 //            remainder theorem the keys of one bucket then differ mod mbar.
 //   order    buckets {p : p mod rbar = q}, largest first, ties by linear q.
 //   offsets  per bucket, the first that puts every key on a free slot among
@@ -222,8 +223,9 @@ int resolve_threads(int requested) {
 
 void build_psh_level(PshLevel& L, const inrf_psh_params& p) {
     const int64_t n = int64_t(L.keys.size()), N = L.res;
-    int64_t mbar = icbrt_ceil(100 * std::max<int64_t>(n, 1), p.load_pct);
-    int64_t rbar = fix_rbar(icbrt_ceil(std::max<int64_t>(n, 1), p.bucket_keys), mbar, N);
+    // mbar * 1024 >= N + 1 keeps rbar <= 1024 for any key count
+    int64_t mbar = std::max(icbrt_ceil(100 * std::max<int64_t>(n, 1), p.load_pct), (N + 1 + 1023) / 1024);
+    int64_t rbar = fix_rbar(std::max<int64_t>(2, icbrt_ceil(std::max<int64_t>(n, 1), p.bucket_keys)), mbar, N);
     int restarts = 0;
     for (;;) {
         for (int r = 0; r <= p.max_restarts; ++r) {

@@ -130,12 +130,13 @@ __device__ __forceinline__ float hit_triangle(const RayPre& R, const float3 v0, 
     return T / det;
 }
 
-// Slab test against [lo, hi] for t in [0, tmax]; conservative by 2*gamma(3)
+// Slab test of one child box for t in [0, tmax]; conservative by 2*gamma(3)
 // (Ize 2013) so that rounding never rejects a box a ray touches.
-__device__ __forceinline__ bool hit_box(const RayPre& R, const float* lo, const float* hi, float tmax, float& tnear) {
-    const float t0x = (lo[0] - R.o.x) * R.inv.x, t1x = (hi[0] - R.o.x) * R.inv.x;
-    const float t0y = (lo[1] - R.o.y) * R.inv.y, t1y = (hi[1] - R.o.y) * R.inv.y;
-    const float t0z = (lo[2] - R.o.z) * R.inv.z, t1z = (hi[2] - R.o.z) * R.inv.z;
+__device__ __forceinline__ bool hit_box(const RayPre& R, float lx, float ly, float lz, float hx, float hy, float hz,
+                                        float tmax, float& tnear) {
+    const float t0x = (lx - R.o.x) * R.inv.x, t1x = (hx - R.o.x) * R.inv.x;
+    const float t0y = (ly - R.o.y) * R.inv.y, t1y = (hy - R.o.y) * R.inv.y;
+    const float t0z = (lz - R.o.z) * R.inv.z, t1z = (hz - R.o.z) * R.inv.z;
     const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.f));
     const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
     tnear = tn;
@@ -159,9 +160,11 @@ __device__ __forceinline__ void leaf(const RayPre& R, const BvhTri* __restrict__
     }
 }
 
-// Closest hit through the BVH; `stack` is this lane's column of an LDS stack
-// with stride kThreads and m.stack_depth entries (a hierarchy of depth D
-// pushes at most D - 1 entries).
+// Closest hit through the four-wide BVH.  At a node, hit leaves are
+// intersected at once; of the hit interior children the nearest (by entry
+// distance) is visited next and the others are pushed farthest first.
+// `stack` is this lane's column of an LDS stack with stride kThreads and
+// m.stack_depth entries (the image's bound).
 __device__ void closest_hit(const ModelC& m, const RayPre& R, int* stack, float& best_t, int32_t& best_i) {
     best_t = INFINITY;
     best_i = -1;
@@ -171,29 +174,48 @@ __device__ void closest_hit(const ModelC& m, const RayPre& R, int* stack, float&
     // termination for a corrupt one
     for (int visits = 0; visits < (1 << 20); ++visits) {
         const float4* p = reinterpret_cast<const float4*>(m.nodes + node);
-        const float4 q0 = p[0], q1 = p[1], q2 = p[2], q3 = p[3];
-        const float lmin[3] = {q0.x, q0.y, q0.z}, lmax[3] = {q0.w, q1.x, q1.y};
-        const float rmin[3] = {q1.z, q1.w, q2.x}, rmax[3] = {q2.y, q2.z, q2.w};
-        const int32_t left = __float_as_int(q3.x), right = __float_as_int(q3.y);
-        float tl, tr;
-        bool hl = hit_box(R, lmin, lmax, best_t, tl);
-        bool hr = hit_box(R, rmin, rmax, best_t, tr);
-        if (hl && left < 0) {
-            leaf(R, m.tris, left, best_t, best_i);
-            hl = false;
+        const float4 lx = p[0], ly = p[1], lz = p[2], hx = p[3], hy = p[4], hz = p[5];
+        const int4 ch = *reinterpret_cast<const int4*>(p + 6);
+        const int32_t ref[4] = {ch.x, ch.y, ch.z, ch.w};
+        float tn[4];
+        bool h[4];
+        h[0] = hit_box(R, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, best_t, tn[0]);
+        h[1] = hit_box(R, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, best_t, tn[1]);
+        h[2] = hit_box(R, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, best_t, tn[2]);
+        h[3] = hit_box(R, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, best_t, tn[3]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            h[c] = h[c] && ref[c] != kBvhEmpty;
+            if (h[c] && ref[c] < 0) {
+                leaf(R, m.tris, ref[c], best_t, best_i);
+                h[c] = false;
+            }
         }
-        if (hr && right < 0) {
-            leaf(R, m.tris, right, best_t, best_i);
-            hr = false;
+        // order the hit interior children by entry distance (misses sort last)
+        float d[4];
+        int32_t r[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            d[c] = h[c] ? tn[c] : INFINITY;
+            r[c] = h[c] ? ref[c] : kBvhEmpty;
         }
-        if (hl && hr && sp < m.stack_depth) {
-            const bool lfirst = tl <= tr;
-            stack[(sp++) * kThreads] = lfirst ? right : left;
-            node = lfirst ? left : right;
-        } else if (hl) {
-            node = left;
-        } else if (hr) {
-            node = right;
+#define INRF_CSWAP(a, b)                                     \
+    if (d[b] < d[a]) {                                       \
+        const float td = d[a]; d[a] = d[b]; d[b] = td;       \
+        const int32_t tr = r[a]; r[a] = r[b]; r[b] = tr;     \
+    }
+        INRF_CSWAP(0, 1)
+        INRF_CSWAP(2, 3)
+        INRF_CSWAP(0, 2)
+        INRF_CSWAP(1, 3)
+        INRF_CSWAP(1, 2)
+#undef INRF_CSWAP
+        // push the farther ones, farthest first, then visit the nearest
+#pragma unroll
+        for (int c = 3; c >= 1; --c)
+            if (r[c] != kBvhEmpty && sp < m.stack_depth) stack[(sp++) * kThreads] = r[c];
+        if (r[0] != kBvhEmpty) {
+            node = r[0];
         } else {
             if (sp == 0) break;
             node = stack[(--sp) * kThreads];
@@ -434,23 +456,23 @@ ModelC make_model(const inrf_model* m, bool need_table, bool need_bvh) {
     if (need_bvh) {
         require(m->n_tris >= 0, "n_tris must be >= 0");
         require(m->n_tris == 0 || (m->bvh_nodes && m->bvh_tris), "bvh images must be set");
-        require(m->n_tris == 0 || (m->bvh_depth >= 1 && m->bvh_depth <= kBvhMaxDepth),
-                "bvh_depth must be the image's depth (1..32)");
-        c.stack_depth = std::max(1, m->bvh_depth - 1);
+        require(m->n_tris == 0 || (m->bvh_stack >= 1 && m->bvh_stack <= kBvhMaxStack),
+                "bvh_stack must be the image's stack bound (1..64)");
+        c.stack_depth = std::max(1, m->bvh_stack);
     }
     for (int l = 0; l < m->n_levels; ++l) {
         const inrf_level_desc& d = m->levels[l];
         require(d.res >= 1 && d.res <= 4096, "level resolution must be in [1, 4096]");
-        require(d.mbar >= 1 && d.mbar <= 1024, "mbar must be in [1, 1024]");
-        require(d.rbar >= 1 && d.rbar <= 4096, "rbar must be in [1, 4096]");
+        require(d.mbar >= 2 && d.mbar <= 1024, "mbar must be in [2, 1024]");
+        require(d.rbar >= 2 && d.rbar <= 1024, "rbar must be in [2, 1024]");
         require(int64_t(d.rbar) * d.rbar * d.rbar < (int64_t(1) << 31), "rbar^3 must fit 31 bits");
         require(d.phi_offset >= 0 && d.slot_offset >= 0, "negative level offsets");
         LevelC& L = c.lv[l];
         L.res = d.res;
         L.mbar = d.mbar;
         L.rbar = d.rbar;
-        L.inv_mbar = 1.f / float(d.mbar);
-        L.inv_rbar = 1.f / float(d.rbar);
+        L.magic_mbar = uint32_t(((uint64_t(1) << 32) + uint64_t(d.mbar) - 1) / uint64_t(d.mbar));
+        L.magic_rbar = uint32_t(((uint64_t(1) << 32) + uint64_t(d.rbar) - 1) / uint64_t(d.rbar));
         L.phi_off = d.phi_offset;
         L.slot_off = d.slot_offset;
     }

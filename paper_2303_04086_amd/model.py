@@ -91,6 +91,7 @@ class BvhImage:
     tris: np.ndarray   # uint8
     n_nodes: int
     depth: int
+    stack: int
 
 
 def build_bvh(verts, tris) -> BvhImage:
@@ -101,10 +102,10 @@ def build_bvh(verts, tris) -> BvhImage:
     try:
         info = L.BvhInfo()
         L.check(lib.inrf_bvh_get_info(h, ctypes.byref(info)))
-        nodes = np.zeros(max(info.node_bytes, 64), np.uint8)
+        nodes = np.zeros(max(info.node_bytes, 128), np.uint8)
         tri = np.zeros(max(info.tri_bytes, 48), np.uint8)
         L.check(lib.inrf_bvh_copy(h, L.ptr(nodes), L.ptr(tri)))
-        return BvhImage(nodes, tri, info.n_nodes, info.depth)
+        return BvhImage(nodes, tri, info.n_nodes, info.depth, info.stack)
     finally:
         lib.inrf_bvh_free(h)
 
@@ -188,7 +189,7 @@ class Renderer:
             m.bvh_nodes = self.bvh_nodes.data_ptr()
             m.bvh_tris = self.bvh_tris.data_ptr()
             m.n_tris = self.n_tris
-            m.bvh_depth = self.bvh.depth
+            m.bvh_stack = self.bvh.stack
             self._descs[table] = m
         return self._descs[table]
 

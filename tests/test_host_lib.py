@@ -65,8 +65,8 @@ def test_occupancy_identical_to_oracle_on_random_soup():
 def test_bvh_invariants(tiny):
     v, t = synth.displaced_sphere(12)
     b = P.build_bvh(v, t)
-    nodes = b.nodes.view(np.float32).reshape(-1, 16)
-    refs = b.nodes.view(np.int32).reshape(-1, 16)[:, 12:14]
+    f = b.nodes.view(np.float32).reshape(-1, 32)
+    refs = b.nodes.view(np.int32).reshape(-1, 32)[:, 24:28]
     tri_img = b.tris.view(np.float32).reshape(-1, 12)
     idx = b.tris.view(np.int32).reshape(-1, 12)[:, 3]
     assert sorted(idx.tolist()) == list(range(len(t)))          # every triangle exactly once
@@ -74,26 +74,37 @@ def test_bvh_invariants(tiny):
     assert np.array_equal(tri_img[:, 0:3], V[t[idx, 0]]) and np.array_equal(tri_img[:, 8:11], V[t[idx, 2]])
     seen = []
 
-    def walk(ref, lo, hi, depth):
-        if ref < 0:
-            code = ~ref
-            first, count = code >> 3, code & 7
-            assert count <= 4
-            for i in range(first, first + count):
-                p = tri_img[i].reshape(3, 4)[:, :3]
-                assert np.all(p >= lo) and np.all(p <= hi)
-                seen.append(i)
-            return depth
-        n = nodes[ref]
-        d = 0
-        for side, (a, z) in enumerate(((n[0:3], n[3:6]), (n[6:9], n[9:12]))):
+    def walk(node, lo, hi, depth):
+        """Returns (deepest leaf level, traversal stack need) of the subtree."""
+        n = f[node]
+        deepest, need, interior = depth, 0, 0
+        for c in range(4):
+            ref = refs[node][c]
+            if ref == -1:
+                continue
+            a = np.array([n[c], n[4 + c], n[8 + c]])
+            z = np.array([n[12 + c], n[16 + c], n[20 + c]])
             if lo is not None:
-                assert np.all(a >= lo) and np.all(z <= hi)          # children inside the parent
-            d = max(d, walk(refs[ref][side], a, z, depth + 1))
-        return d
+                assert np.all(a >= lo) and np.all(z <= hi)           # children inside the parent
+            if ref < 0:
+                code = ~ref
+                first, count = code >> 3, code & 7
+                assert 1 <= count <= 4
+                for i in range(first, first + count):
+                    p = tri_img[i].reshape(3, 4)[:, :3]
+                    assert np.all(p >= a) and np.all(p <= z)        # triangles inside the leaf box
+                    seen.append(i)
+                deepest = max(deepest, depth + 1)
+            else:
+                interior += 1
+                d, s = walk(ref, a, z, depth + 1)
+                deepest, need = max(deepest, d), max(need, s)
+        return deepest, max(0, interior - 1) + need
 
-    depth = walk(0, None, None, 1)
-    assert sorted(seen) == list(range(len(t))) and depth <= 32 and depth == b.depth
+    depth, need = walk(0, None, None, 1)
+    assert sorted(seen) == list(range(len(t)))
+    assert depth == b.depth and max(1, need) == b.stack and b.stack <= 64
+    assert b.n_nodes < len(t) / 2                                   # four-wide: far fewer nodes than leaves
 
 
 def test_argument_errors():
@@ -130,5 +141,9 @@ def test_empty_mesh_builds():
     t = np.zeros((0, 3), np.int32)
     lv = P.build_psh(v, t, [4])[0]
     assert len(lv.keys) == 0 and lv.mbar == 2  # smallest with 80*m^3 >= 100*max(n, 1)
+    # few keys at a large resolution: library and oracle agree on the raised sizes
+    lv = P.build_psh_keys(4000, [((17 * 4001) + 0) * 4001 + 3999])
+    O = oracle.build_psh_level(np.array([[3999, 0, 17]]), 4000, seed=1)
+    assert (lv.mbar, lv.rbar) == (O.mbar, O.rbar) and np.array_equal(lv.phi, O.phi)
     b = P.build_bvh(v, t)
-    assert b.n_nodes == 1
+    assert b.n_nodes == 1 and b.stack == 1

@@ -18,6 +18,7 @@ def test_sizes_follow_rules(tiny, tiny_keys, levels):
         n = len(k)
         assert 80 * L.mbar ** 3 >= 100 * n > 80 * (L.mbar - 1) ** 3
         assert gcd(L.mbar, L.rbar) == 1 and L.mbar * L.rbar >= N + 1 and 2 * L.rbar ** 3 >= n
+        assert 2 <= L.rbar <= 1024 and 1024 * L.mbar >= N + 1
         assert L.phi.shape == (L.rbar ** 3,)
         off = np.stack([L.phi & 1023, (L.phi >> 10) & 1023, (L.phi >> 20) & 1023], 1)
         assert off.max() < L.mbar and (L.phi >> 30).max() == 0
@@ -86,6 +87,13 @@ def test_tiny_hand_case():
     assert int(used[0]) == (r % 2) | (((r >> 21) % 2) << 10) | (((r >> 42) % 2) << 20)
     s = L.slots.tolist()
     assert all(s[i + 1] == s[i] + 1 for i in range(0, 8, 2))
+
+
+def test_sizes_at_large_resolution_with_few_keys():
+    # one key at N = 4000: mbar is raised so that rbar stays <= 1024
+    L = oracle.build_psh_level(np.array([[3999, 0, 17]]), 4000, seed=1)
+    assert L.mbar == 4 and L.rbar <= 1024 and L.mbar * L.rbar >= 4001
+    assert L.slots.tolist() == oracle.psh_slots(L, [[3999, 0, 17]]).tolist()
 
 
 def test_splitmix64_published_vector():
