@@ -28,10 +28,11 @@ from .encode import grid_cell, trilinear_encode, FeatureGrid
 from .sh import sh_real
 from .mlp import mlp_forward
 from .render import Model, render_rays, render_camera, encode_points
+from .backward import backward_rays, mse_loss, mse_grad
 
 __all__ = [
     "camera_rays", "closest_hit", "HitResult", "surface_cells", "shell_keys",
     "build_psh_level", "psh_slots", "PSHLevel", "grid_cell", "trilinear_encode",
     "FeatureGrid", "sh_real", "mlp_forward", "Model", "render_rays",
-    "render_camera", "encode_points",
+    "render_camera", "encode_points", "backward_rays", "mse_loss", "mse_grad",
 ]

@@ -2,29 +2,33 @@
 // d_in -> 64 -> 64 -> 4, no biases, ReLU hidden, sigmoid outputs.
 //
 // Lane layout (both precisions).  A wave evaluates 16 rays at a time; lane
-// l = 16g + r works on ray r of the block and owns one quarter of that ray's
-// inputs: the features of levels g, g+4, g+8, ... and SH values 4g..4g+3.
-// These are exactly the values lane l must supply as the B operand of the
-// 16x16 matrix instructions (B[k][r] with k in lane group g's slice), so the
-// encoding never leaves registers.  The order in which each lane's values
-// enter the reduction is a permutation of the natural input order [E_0..E_{L-1},
-// SH_0..SH_15]; the first layer's weights are stored in LDS in that permuted
-// order ("fragment order").
+// l = 16g + r supplies B[k][r] for the k of its lane group g, i.e. a quarter
+// of ray r's first-layer inputs.  The caller places the F feature slots (2 per
+// level, zero-padded) of the block's rays in an LDS tile, one row per ray, and
+// each lane reads its slice with 16-byte loads; the 16 SH values are computed
+// by the lanes themselves.  The order in which values enter the reduction is a
+// permutation of the natural input order [E_0..E_{L-1}, SH_0..SH_15]; the
+// first layer's weights are stored in LDS in that permuted order ("fragment
+// order"):
+//   FP32 (v_mfma_f32_16x16x4f32, one value per lane per instruction): step
+//     s = 4j + i carries feature slot 16j + 4g + i; the last four steps carry
+//     SH value 4g + i.
+//   FP16/BF16 (v_mfma_f32_16x16x32, eight values per lane): chunk c carries
+//     feature slots 32c + 8g + i; the last chunk carries SH value 8g + i
+//     (g < 2; zeros for g >= 2).
 //
 // The result of a 16x16 instruction, D[4g'+i][r] held by lane (g', r) as
 // element i of tile mt, is hidden unit 16mt + 4g' + i of ray r.  The next layer
 // takes its B operand from those registers unchanged by ordering its
 // reduction index the same way; its weights are stored in that order too.
-//
-// FP32 uses v_mfma_f32_16x16x4f32 (one value per lane per instruction); FP16
-// and BF16 use v_mfma_f32_16x16x32_{f16,bf16} (eight values per lane), with
-// FP32 accumulation throughout.
+// Accumulation is FP32 throughout.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 #include <hip/hip_bf16.h>
 
+#include "device_common.hpp"
 #include "inrf.h"
 
 namespace inrf {
@@ -37,21 +41,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int kHidden = INRF_HIDDEN;
 
 __device__ __forceinline__ float sigmoidf(float z) { return 1.f / (1.f + __expf(-z)); }
-
-// Values one lane holds for the first layer: 2 features for each of its LPG
-// levels, then 4 SH values.
-__host__ __device__ constexpr int lane_inputs(int lpg) { return 2 * lpg + 4; }
-
-// Natural input index of value v (0 <= v < lane_inputs) of lane group g, or
-// -1 for padding (a level beyond L).
-__device__ __forceinline__ int input_index(int g, int v, int lpg, int n_levels) {
-    if (v < 2 * lpg) {
-        const int level = g + 4 * (v / 2);
-        return level < n_levels ? 2 * level + (v & 1) : -1;
-    }
-    if (v < 2 * lpg + 4) return 2 * n_levels + 4 * g + (v - 2 * lpg);
-    return -1;
-}
 
 // ------------------------------------------------------- precision traits --
 template <class P>
@@ -79,16 +68,39 @@ struct Mfma<__bf16> {
     __device__ static f32x4 op(vec a, vec b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
 };
 
+// Feature slots of a tile row for up to lmax levels, rounded so that every
+// lane's 16-byte reads stay inside the row.
+__host__ __device__ constexpr int feature_slots(int lmax, int V) {
+    return V == 1 ? ((2 * lmax + 15) / 16) * 16 : ((2 * lmax + 31) / 32) * 32;
+}
 // Number of first-layer instructions per output tile.
-__host__ __device__ constexpr int l1_steps(int lpg, int V) { return (lane_inputs(lpg) + V - 1) / V; }
+__host__ __device__ constexpr int l1_steps(int F, int V) { return V == 1 ? F / 4 + 4 : F / 32 + 1; }
 // Steps of layers 2 and 3 (K = 64).
 __host__ __device__ constexpr int hid_steps(int V) { return V == 1 ? 16 : 2; }
 // LDS image, in units of one lane's operand (P::vec), 64 lanes per fragment:
 //   W1 fragments (mt, s), W2 fragments (ot, s), W3 fragments (s).
-__host__ __device__ constexpr int weight_vecs(int lpg, int V) {
-    return 64 * (4 * l1_steps(lpg, V) + 4 * hid_steps(V) + hid_steps(V));
+__host__ __device__ constexpr int weight_vecs(int F, int V) {
+    return 64 * (4 * l1_steps(F, V) + 4 * hid_steps(V) + hid_steps(V));
 }
-__host__ __device__ constexpr int weight_bytes(int lpg, int V) { return weight_vecs(lpg, V) * (V == 1 ? 4 : 16); }
+__host__ __device__ constexpr int weight_bytes(int F, int V) { return weight_vecs(F, V) * (V == 1 ? 4 : 16); }
+
+// Natural input index carried by element i of lane group g at first-layer
+// step s, or -1 for padding (n_levels real levels, F feature slots).
+__device__ __forceinline__ int l1_index(int V, int F, int n_levels, int s, int g, int i) {
+    if (V == 1) {
+        if (s < F / 4) {
+            const int slot = 16 * (s / 4) + 4 * g + (s % 4);
+            return slot < 2 * n_levels ? slot : -1;
+        }
+        return 2 * n_levels + 4 * g + (s - F / 4);
+    }
+    if (s < F / 32) {
+        const int slot = 32 * s + 8 * g + i;
+        return slot < 2 * n_levels ? slot : -1;
+    }
+    const int k = 8 * g + i;
+    return k < INRF_SH_DIM ? 2 * n_levels + k : -1;
+}
 
 // Hidden unit fed by element i of lane group g at hidden-layer step s.
 __device__ __forceinline__ int hidden_index(int V, int s, int g, int i) {
@@ -97,7 +109,7 @@ __device__ __forceinline__ int hidden_index(int V, int s, int g, int i) {
 }
 
 template <class P>
-__device__ inline void stage_weights(const float* __restrict__ w, int n_levels, int lpg,
+__device__ inline void stage_weights(const float* __restrict__ w, int n_levels, int F,
                                      typename Mfma<P>::vec* __restrict__ lds) {
     typedef Mfma<P> M;
     constexpr int V = M::V;
@@ -105,7 +117,7 @@ __device__ inline void stage_weights(const float* __restrict__ w, int n_levels, 
     const float* W1 = w;
     const float* W2 = w + kHidden * d_in;
     const float* W3 = W2 + kHidden * kHidden;
-    const int S1 = l1_steps(lpg, V), SH = hid_steps(V);
+    const int S1 = l1_steps(F, V), SH = hid_steps(V);
     const int n1 = 64 * 4 * S1, n2 = 64 * 4 * SH, n3 = 64 * SH;
     for (int e = threadIdx.x; e < n1 + n2 + n3; e += blockDim.x) {
         const int lane = e % 64, g = lane / 16, r = lane % 16;
@@ -113,7 +125,7 @@ __device__ inline void stage_weights(const float* __restrict__ w, int n_levels, 
         if (e < n1) {
             const int f = e / 64, mt = f / S1, s = f % S1;
             for (int i = 0; i < V; ++i) {
-                const int k = input_index(g, s * V + i, lpg, n_levels);
+                const int k = l1_index(V, F, n_levels, s, g, i);
                 const float x = k >= 0 ? W1[(16 * mt + r) * d_in + k] : 0.f;
                 if constexpr (V == 1) v = M::cvt(x);
                 else v[i] = M::cvt(x);
@@ -137,29 +149,59 @@ __device__ inline void stage_weights(const float* __restrict__ w, int n_levels, 
     }
 }
 
-// The network for this lane's block of 16 rays.  `in` holds this lane's
-// first-layer values (lane_inputs(LPG) of them, FP32).  Returns D of the
-// output tile: for lanes l < 16, element i is pre-sigmoid output i of ray l.
-template <class P, int LPG>
-__device__ __forceinline__ f32x4 mlp_block(const typename Mfma<P>::vec* __restrict__ W, const float* in) {
+// The first layer's B operands of this lane: feature slots from row r of the
+// block's LDS tile (element type of the precision for FP16/BF16, FP32
+// otherwise) and the SH values of direction d (ray r of the block).
+template <class P, int F>
+__device__ __forceinline__ void load_inputs(const void* tile_row, float dx, float dy, float dz,
+                                            typename Mfma<P>::vec* b) {
+    typedef Mfma<P> M;
+    constexpr int V = M::V, S1 = l1_steps(F, V);
+    const int g = __lane_id() >> 4;
+    float sh[16];
+    sh16(dx, dy, dz, sh);
+    if constexpr (V == 1) {
+        const float* row = reinterpret_cast<const float*>(tile_row);
+#pragma unroll
+        for (int j = 0; j < F / 16; ++j) {
+            const f32x4 v = *reinterpret_cast<const f32x4*>(row + 16 * j + 4 * g);
+            b[4 * j + 0] = v[0];
+            b[4 * j + 1] = v[1];
+            b[4 * j + 2] = v[2];
+            b[4 * j + 3] = v[3];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            b[F / 4 + i] = g == 0 ? sh[i] : (g == 1 ? sh[4 + i] : (g == 2 ? sh[8 + i] : sh[12 + i]));
+    } else {
+        typedef typename M::vec Vec;
+        const Vec* row = reinterpret_cast<const Vec*>(tile_row);
+#pragma unroll
+        for (int c = 0; c < F / 32; ++c) b[c] = row[4 * c + g];
+        Vec v;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = M::cvt(g == 0 ? sh[i] : (g == 1 ? sh[8 + i] : 0.f));
+        b[S1 - 1] = v;
+    }
+}
+
+// The network for this lane's block of 16 rays given its first-layer B
+// operands.  Returns D of the output tile: for lanes l < 16, element i is
+// pre-sigmoid output i of ray l.
+template <class P, int F>
+__device__ __forceinline__ f32x4 mlp_block(const typename Mfma<P>::vec* __restrict__ W,
+                                           const typename Mfma<P>::vec* b1) {
     typedef Mfma<P> M;
     typedef typename M::vec Vec;
-    constexpr int V = M::V, S1 = l1_steps(LPG, V), SH = hid_steps(V), NI = lane_inputs(LPG);
+    constexpr int V = M::V, S1 = l1_steps(F, V), SH = hid_steps(V);
     const int lane = __lane_id();
     f32x4 h1[4];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) h1[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < S1; ++s) {
-        Vec b;
-        if constexpr (V == 1) {
-            b = in[s];
-        } else {
 #pragma unroll
-            for (int i = 0; i < V; ++i) b[i] = M::cvt(s * V + i < NI ? in[s * V + i] : 0.f);
-        }
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt) h1[mt] = M::op(W[(mt * S1 + s) * 64 + lane], b, h1[mt]);
+        for (int mt = 0; mt < 4; ++mt) h1[mt] = M::op(W[(mt * S1 + s) * 64 + lane], b1[s], h1[mt]);
         __builtin_amdgcn_sched_barrier(0);  // keep weight loads next to their use
     }
     const Vec* W2 = W + 64 * 4 * S1;

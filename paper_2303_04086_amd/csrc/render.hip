@@ -294,79 +294,101 @@ __global__ void k_reset(int32_t* counter) {
 
 // ------------------------------------------------------------- shading ----
 
-// Stages the weights (fragment order) and the level table into LDS; returns
-// the LDS level table.
-template <class P, int LPG>
-__device__ inline const LevelC* stage_model(const ModelC& m, typename Mfma<P>::vec* W) {
-    stage_weights<P>(m.weights, m.n_levels, LPG, W);
-    LevelC* lv = reinterpret_cast<LevelC*>(reinterpret_cast<char*>(W) + weight_bytes(LPG, Mfma<P>::V));
-    if (threadIdx.x == 0)
-        for (int l = 0; l < m.n_levels; ++l) lv[l] = m.lv[l];
-    __syncthreads();
-    return lv;
-}
+template <class P>
+struct TileElem {
+    typedef P type;  // FP16/BF16 tiles hold the MMA operand type
+};
+template <>
+struct TileElem<float> {
+    typedef float type;
+};
 
-__host__ __device__ constexpr size_t shade_lds_bytes(int lpg, int V) {
-    return size_t(weight_bytes(lpg, V)) + sizeof(LevelC) * INRF_MAX_LEVELS;
-}
-
-// This lane's first-layer values for hit point (x, y, z) and unit direction
-// d: features of levels g, g+4, ..., then SH values 4g..4g+3.  Levels are
-// fetched two at a time so their offset loads are in flight together; a lane
-// whose level lies beyond L looks up level 0 and drops the result.
-template <class TableT, int LPG>
-__device__ __forceinline__ void lane_features(const ModelC& m, const LevelC* lv, int g, float x, float y, float z,
-                                              float dx, float dy, float dz, float* in) {
-#pragma unroll
-    for (int j = 0; j < LPG; j += 2) {
-        const int la = g + 4 * j;
-        const bool va = la < m.n_levels;
-        if (j + 1 < LPG) {
-            const int lb = la + 4;
-            const bool vb = lb < m.n_levels;
-            float2 ea, eb;
-            encode_level_pair<TableT>(m, lv[va ? la : 0], lv[vb ? lb : 0], x, y, z, ea, eb);
-            in[2 * j] = va ? ea.x : 0.f;
-            in[2 * j + 1] = va ? ea.y : 0.f;
-            in[2 * j + 2] = vb ? eb.x : 0.f;
-            in[2 * j + 3] = vb ? eb.y : 0.f;
-            __builtin_amdgcn_sched_barrier(0);  // one pair of levels in flight at a time
-        } else {
-            const float2 ea = encode_level<TableT>(m, lv[va ? la : 0], x, y, z, nullptr);
-            in[2 * j] = va ? ea.x : 0.f;
-            in[2 * j + 1] = va ? ea.y : 0.f;
-        }
+// Encoded features of levels L .. LMAX-1 of one point into e[2L ..], two
+// levels at a time so that the offset loads of both are in flight before
+// either is waited on.  Written as a recursion rather than a loop so that
+// every level index stays a compile-time constant (the features stay in
+// registers) at any level count.
+template <class TableT, int L, int LMAX, int F>
+__device__ __forceinline__ void gather_levels(const ModelC& m, float x, float y, float z, float (&e)[F]) {
+    if constexpr (L < LMAX) {
+        float2 ea = make_float2(0.f, 0.f), eb = make_float2(0.f, 0.f);
+        if (L + 1 < m.n_levels) encode_level_pair<TableT>(m, m.lv[L], m.lv[L + 1], x, y, z, ea, eb);
+        else if (L < m.n_levels) ea = encode_level<TableT>(m, m.lv[L], x, y, z, nullptr);
+        e[2 * L] = ea.x;
+        e[2 * L + 1] = ea.y;
+        e[2 * L + 2] = eb.x;
+        e[2 * L + 3] = eb.y;
+        __builtin_amdgcn_sched_barrier(0);  // one pair of levels in flight at a time
+        gather_levels<TableT, L + 2, LMAX>(m, x, y, z, e);
     }
-    float sh[16];
-    sh16(dx, dy, dz, sh);
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-        in[2 * LPG + i] = g == 0 ? sh[i] : (g == 1 ? sh[4 + i] : (g == 2 ? sh[8 + i] : sh[12 + i]));
 }
 
-// Persistent waves over the packed hit list, 16 hits per wave step.
+// Geometry of the per-wave LDS tile: 16 rows (rays) of F feature slots.
+template <class P, int LPG>
+struct ShadeShape {
+    static constexpr int V = Mfma<P>::V;
+    static constexpr int LMAX = 4 * LPG;  // levels the instantiation handles
+    static constexpr int F = feature_slots(LMAX, V);
+    static constexpr int STRIDE = F + (V == 1 ? 4 : 8);  // elements per row, keeps 16-byte alignment
+    static constexpr int S1 = l1_steps(F, V);
+    static constexpr size_t tile_bytes = 16 * STRIDE * sizeof(typename TileElem<P>::type);
+    static constexpr size_t lds_bytes = size_t(weight_bytes(F, V)) + (kThreads / 64) * tile_bytes;
+};
+
+// Persistent waves over the packed hit list, 64 hits per wave step.  Each
+// lane gathers every level of its own hit (a level's loads then cover 64
+// neighbouring rays, and level parameters are wave-uniform), two levels at a
+// time so their offset loads are in flight together.  The network then runs
+// on four blocks of 16 rays; each block's features pass through the wave's
+// LDS tile into the matrix-core B-operand layout.
 template <class TableT, class P, int LPG>
 __global__ __launch_bounds__(kThreads) void k_shade(ModelC m, const HitRec* __restrict__ recs,
                                                     const int32_t* __restrict__ counter, float* __restrict__ rgba) {
+    typedef Mfma<P> M;
+    typedef typename M::vec Vec;
+    typedef ShadeShape<P, LPG> S;
+    typedef typename TileElem<P>::type T;
     extern __shared__ float4 lds_v[];
-    typedef typename Mfma<P>::vec Vec;
     Vec* W = reinterpret_cast<Vec*>(lds_v);
-    const LevelC* lv = stage_model<P, LPG>(m, W);
+    stage_weights<P>(m.weights, m.n_levels, S::F, W);
+    T* tile = reinterpret_cast<T*>(reinterpret_cast<char*>(lds_v) + weight_bytes(S::F, S::V) +
+                                   (threadIdx.x / 64) * S::tile_bytes);
+    __syncthreads();
     const int n = *counter;
     const int lane = __lane_id(), g = lane >> 4, r = lane & 15;
-    const int64_t n_waves = int64_t(gridDim.x) * (kThreads / 64);
-    for (int64_t blk = int64_t(blockIdx.x) * (kThreads / 64) + threadIdx.x / 64; blk * 16 < n; blk += n_waves) {
-        const int64_t i = blk * 16 + r;
+    for (int64_t base = (int64_t(blockIdx.x) * (kThreads / 64) + threadIdx.x / 64) * 64; base < n;
+         base += int64_t(gridDim.x) * kThreads) {
+        const int64_t i = base + lane;
         const bool act = i < n;
         HitRec h;
         if (act) h = recs[i];
         else h = HitRec{0.f, 0.f, 0.f, 0, 0.f, 0.f, 1.f, 0};
-        float in[lane_inputs(LPG)];
-        lane_features<TableT, LPG>(m, lv, g, h.x, h.y, h.z, h.dx, h.dy, h.dz, in);
-        const f32x4 o = mlp_block<P, LPG>(W, in);
-        if (g == 0 && act)
-            reinterpret_cast<float4*>(rgba)[h.out] =
-                make_float4(sigmoidf(o[0]), sigmoidf(o[1]), sigmoidf(o[2]), sigmoidf(o[3]));
+        float e[S::F];
+#pragma unroll
+        for (int k = 2 * S::LMAX; k < S::F; ++k) e[k] = 0.f;
+        gather_levels<TableT, 0, S::LMAX>(m, h.x, h.y, h.z, e);
+        const int nb = int(min<int64_t>(4, (int64_t(n) - base + 15) / 16));
+        for (int b = 0; b < nb; ++b) {
+            if (g == b) {
+                T* row = tile + r * S::STRIDE;
+#pragma unroll
+                for (int k = 0; k < S::F; ++k) row[k] = T(e[k]);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int src = 16 * b + r;
+            Vec b1[S::S1];
+            load_inputs<P, S::F>(tile + r * S::STRIDE, __shfl(h.dx, src), __shfl(h.dy, src), __shfl(h.dz, src), b1);
+            const int out = __shfl(h.out, src);
+            const f32x4 o = mlp_block<P, S::F>(W, b1);
+            if (g == 0 && base + src < n)
+                reinterpret_cast<float4*>(rgba)[out] =
+                    make_float4(sigmoidf(o[0]), sigmoidf(o[1]), sigmoidf(o[2]), sigmoidf(o[3]));
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();  // the tile is rewritten by the next block
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
     }
 }
 
@@ -385,30 +407,62 @@ __global__ __launch_bounds__(kThreads) void k_encode(ModelC m, const float* __re
     }
 }
 
-// The network alone on caller inputs [n][d_in] in natural order.
+// The network alone on caller inputs [n][d_in] in natural order: each
+// 16-ray block is staged through the wave's LDS tile like k_shade's.
 template <class P, int LPG>
 __global__ __launch_bounds__(kThreads) void k_mlp(ModelC m, const float* __restrict__ x, int64_t n,
                                                   float* __restrict__ rgba) {
+    typedef Mfma<P> M;
+    typedef typename M::vec Vec;
+    typedef ShadeShape<P, LPG> S;
+    typedef typename TileElem<P>::type T;
     extern __shared__ float4 lds_v[];
-    typedef typename Mfma<P>::vec Vec;
     Vec* W = reinterpret_cast<Vec*>(lds_v);
-    stage_model<P, LPG>(m, W);
+    stage_weights<P>(m.weights, m.n_levels, S::F, W);
+    T* tile = reinterpret_cast<T*>(reinterpret_cast<char*>(lds_v) + weight_bytes(S::F, S::V) +
+                                   (threadIdx.x / 64) * S::tile_bytes);
+    __syncthreads();
     const int d_in = 2 * m.n_levels + INRF_SH_DIM;
-    const int lane = __lane_id(), g = lane >> 4, r = lane & 15;
-    const int64_t n_waves = int64_t(gridDim.x) * (kThreads / 64);
-    for (int64_t blk = int64_t(blockIdx.x) * (kThreads / 64) + threadIdx.x / 64; blk * 16 < n; blk += n_waves) {
-        const int64_t i = blk * 16 + r;
-        const bool act = i < n;
-        float in[lane_inputs(LPG)];
-#pragma unroll
-        for (int v = 0; v < lane_inputs(LPG); ++v) {
-            const int k = input_index(g, v, LPG, m.n_levels);
-            in[v] = (act && k >= 0) ? x[i * d_in + k] : 0.f;
+    const int lane = __lane_id(), r = lane & 15;
+    for (int64_t blk = int64_t(blockIdx.x) * (kThreads / 64) + threadIdx.x / 64; blk * 16 < n;
+         blk += int64_t(gridDim.x) * (kThreads / 64)) {
+        // rows of the tile: 16 rays x F feature slots, 4 lanes per row
+        for (int k = lane; k < 16 * S::F; k += 64) {
+            const int row = k / S::F, slot = k % S::F;
+            const int64_t ray = blk * 16 + row;
+            tile[row * S::STRIDE + slot] = T((ray < n && slot < 2 * m.n_levels) ? x[ray * d_in + slot] : 0.f);
         }
-        const f32x4 o = mlp_block<P, LPG>(W, in);
-        if (g == 0 && act)
-            reinterpret_cast<float4*>(rgba)[i] =
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int64_t ray = blk * 16 + r;
+        const bool act = ray < n;
+        // the SH inputs are given, not computed: rebuild them from the caller's values
+        Vec b1[S::S1];
+        load_inputs<P, S::F>(tile + r * S::STRIDE, 0.f, 0.f, 1.f, b1);
+        {
+            const int g = lane >> 4;
+            float shv[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) shv[k] = act ? x[ray * d_in + 2 * m.n_levels + k] : 0.f;
+            if constexpr (S::V == 1) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    b1[S::F / 4 + t] = g == 0 ? shv[t] : (g == 1 ? shv[4 + t] : (g == 2 ? shv[8 + t] : shv[12 + t]));
+            } else {
+                Vec v;
+#pragma unroll
+                for (int t = 0; t < 8; ++t) v[t] = M::cvt(g == 0 ? shv[t] : (g == 1 ? shv[8 + t] : 0.f));
+                b1[S::S1 - 1] = v;
+            }
+        }
+        const f32x4 o = mlp_block<P, S::F>(W, b1);
+        if ((lane >> 4) == 0 && act)
+            reinterpret_cast<float4*>(rgba)[ray] =
                 make_float4(sigmoidf(o[0]), sigmoidf(o[1]), sigmoidf(o[2]), sigmoidf(o[3]));
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -501,7 +555,7 @@ unsigned resident_grid(K kernel, size_t lds) {
 
 template <class TableT, class P, int LPG>
 void launch_shade_t(const ModelC& c, const HitRec* recs, const int32_t* counter, float* rgba, hipStream_t s) {
-    const size_t lds = shade_lds_bytes(LPG, Mfma<P>::V);
+    const size_t lds = ShadeShape<P, LPG>::lds_bytes;
     auto kern = k_shade<TableT, P, LPG>;
     allow_lds(kern, lds);
     hipLaunchKernelGGL(kern, dim3(resident_grid(kern, lds)), dim3(kThreads), lds, s, c, recs, counter, rgba);
@@ -509,10 +563,10 @@ void launch_shade_t(const ModelC& c, const HitRec* recs, const int32_t* counter,
 
 template <class P, int LPG>
 void launch_mlp_t(const ModelC& c, const float* in, int64_t n, float* rgba, hipStream_t s) {
-    const size_t lds = shade_lds_bytes(LPG, Mfma<P>::V);
+    const size_t lds = ShadeShape<P, LPG>::lds_bytes;
     auto kern = k_mlp<P, LPG>;
     allow_lds(kern, lds);
-    const int64_t blocks = (n + 63) / 64;
+    const int64_t blocks = (n + kThreads / 4 - 1) / (kThreads / 4);  // 16 rays per wave step
     const unsigned grid = unsigned(std::min<int64_t>(blocks, resident_grid(kern, lds)));
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, c, in, n, rgba);
 }

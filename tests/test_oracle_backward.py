@@ -1,0 +1,84 @@
+"""Pins of the oracle's loss gradient: FP64 central finite differences.
+
+With h = 1e-6 and a loss of order 0.1, the difference quotient carries a
+rounding error of about eps * L / h ~ 3e-11, so each comparison allows a
+relative error of 1e-5 plus an absolute 1e-10."""
+import copy
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+
+@pytest.fixture(scope="module")
+def setup(tiny):
+    m = oracle.Model.from_workload(tiny, kind="uniform", sigma=0.5)   # features that matter
+    o, d = synth.random_rays(256, 31, spread=0.25)
+    rng = np.random.default_rng(3)
+    target = rng.uniform(0, 1, (256, 4))
+    return m, o.astype(np.float64), d.astype(np.float64), target
+
+
+def _loss(m, o, d, target):
+    return oracle.mse_loss(oracle.render_rays(m, o, d)["rgba"], target)
+
+
+def test_weight_gradient_matches_finite_differences(setup):
+    m, o, d, target = setup
+    rgba = oracle.render_rays(m, o, d)["rgba"]
+    g = oracle.backward_rays(m, o, d, oracle.mse_grad(rgba, target))
+    assert np.array_equal(g["rgba"], rgba)
+    rng = np.random.default_rng(0)
+    h = 1e-6
+    worst = 0.0
+    for layer in range(3):
+        W = m.weights[layer]
+        for _ in range(8):
+            i, j = rng.integers(0, W.shape[0]), rng.integers(0, W.shape[1])
+            mp = copy.copy(m)
+            mp.weights = [w.astype(np.float64).copy() for w in m.weights]
+            mp.weights[layer][i, j] += h
+            lp = _loss(mp, o, d, target)
+            mp.weights[layer][i, j] -= 2 * h
+            lm = _loss(mp, o, d, target)
+            fd = (lp - lm) / (2 * h)
+            an = g["weights"][layer][i, j]
+            worst = max(worst, abs(fd - an) - 1e-5 * abs(an))
+    assert worst < 1e-10, worst
+
+
+def test_feature_gradient_matches_finite_differences(setup):
+    m, o, d, target = setup
+    rgba = oracle.render_rays(m, o, d)["rgba"]
+    g = oracle.backward_rays(m, o, d, oracle.mse_grad(rgba, target))
+    h = 1e-6
+    worst = 0.0
+    for l in (0, 3):
+        grid = m.grids[l]
+        verts = sorted(g["features"][l], key=lambda v: -np.abs(g["features"][l][v]).max())[:6]
+        for v in verts:
+            for f in range(grid.F):
+                old = grid.table[v].copy()
+                grid.table[v] = old + np.eye(grid.F)[f] * h
+                lp = _loss(m, o, d, target)
+                grid.table[v] = old - np.eye(grid.F)[f] * h
+                lm = _loss(m, o, d, target)
+                grid.table[v] = old
+                fd = (lp - lm) / (2 * h)
+                an = g["features"][l][v][f]
+                worst = max(worst, abs(fd - an) - 1e-5 * abs(an))
+    assert worst < 1e-10, worst
+
+
+def test_sigmoid_slope_at_zero():
+    # zero weights: output 0.5 everywhere, dL/dz3 = dL/dy / 4, no gradient below
+    w = synth.workload_tiny()
+    m = oracle.Model(w.verts, w.tris, oracle.Model.from_workload(w).grids,
+                     [np.zeros((64, 24)), np.zeros((64, 64)), np.zeros((4, 64))])
+    o, d = synth.random_rays(16, 5, spread=0.1)
+    gy = np.ones((16, 4))
+    g = oracle.backward_rays(m, o, d, gy)
+    assert np.all(g["weights"][0] == 0) and np.all(g["weights"][1] == 0) and np.all(g["weights"][2] == 0)
+    assert all(len(f) == 0 or all(np.all(v == 0) for v in f.values()) for f in g["features"])
