@@ -158,6 +158,65 @@ def load_traffic(kernel: str):
     return e.get("bytes_per_launch")
 
 
+def sweep_bench(torch, R, w, frames):
+    """The paper's speed-distance protocol: the same object from 8 directions
+    at decreasing distance (hit fraction rising towards a full screen), FP16
+    path; plus 1920x1080 at the headline distance."""
+    import synth
+    out = {}
+    cases = [(f"d{d}", d, w.cameras[0].width, w.cameras[0].height) for d in (2.0, 1.4, 1.0, 0.7)]
+    cases.append(("1080p_d2.0", 2.0, 1920, 1080))
+    for name, dist, W, H in cases:
+        cams = synth.fibonacci_cameras(8, dist, W, H)
+        r = run_frames(torch, R, cams, "fp16", "f16", frames, 2)
+        hits = sum(r["hits"]) / frames
+        shade_s = sum(r["shade_ms"]) / frames / 1e3
+        mlp_tf = hits * mlp_flops(2 * R.n_levels + 16) / shade_s / 1e12
+        out[name] = {"width": W, "height": H, "distance": dist,
+                     "Mrays_per_s": round(W * H * frames / (sum(r["frame_ms"]) / 1e3) / 1e6, 1),
+                     "hit_fraction": round(hits / (W * H), 4),
+                     "trace_ms_avg": round(sum(r["trace_ms"]) / frames, 4),
+                     "shade_ms_avg": round(shade_s * 1e3, 4),
+                     "shade_requested_GBps": round(hits * requested_bytes_per_hit(R.n_levels, "f16") / shade_s / 1e9, 1),
+                     "shade_mlp_TFLOPs": round(mlp_tf, 2),
+                     "shade_mlp_mfma_util": round(mlp_tf / MFMA_PEAK_TFLOPS["fp16"], 4)}
+        log(f"sweep {name}: {out[name]}")
+    return out
+
+
+def train_bench(torch, R, w, steps, batch):
+    """Training steps (Sec. 4.2): batches of rays from 64 viewpoints, MSE on
+    RGBA against seeded stand-in targets, backward, Adam on the FP32 table
+    and weights (FP16 table refreshed)."""
+    import numpy as np
+    import synth
+    from paper_2303_04086_amd.train import Trainer
+    origins = np.stack([c.origin for c in synth.random_cameras(64, 7, 2.0, 64, 64)])
+    batches = []
+    for k in range(4):
+        o, d = synth.view_rays(origins, batch, 100 + k)
+        tgt = np.random.Generator(np.random.PCG64(200 + k)).uniform(0, 1, (batch, 4)).astype(np.float32)
+        batches.append(tuple(torch.from_numpy(a).cuda() for a in (o, d, tgt)))
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    tr = Trainer(R, lr=1e-2, beta1=0.9, beta2=0.99)
+    for k in range(2):
+        tr.step(*batches[k % 4])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(steps):
+        loss = tr.step(*batches[k % 4])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    return {"steps": steps, "batch_rays": batch, "ms_per_step": round(ms, 4), "steps_per_s": round(1e3 / ms, 2),
+            "Mrays_per_s": round(batch / ms / 1e3, 2), "last_loss": round(float(loss), 6),
+            "peak_hbm_GB": round(torch.cuda.max_memory_allocated() / 1e9, 3),
+            "params": int(R.tables["f32"].numel() + R.weights.numel()),
+            "note": "forward + backward + dense Adam over the whole FP32 table each step; stand-in targets"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,6 +228,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mlp", action="store_true")
     ap.add_argument("--mlp-rays", type=int, default=1 << 24)
+    ap.add_argument("--sweep-frames", type=int, default=8, help="frames per sweep case (0: no sweep)")
+    ap.add_argument("--train-steps", type=int, default=10, help="timed training steps (0: none)")
+    ap.add_argument("--train-batch", type=int, default=1 << 18)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times), the reference "
                          "for scaling hardware byte counters, and exit")
@@ -220,6 +282,11 @@ def main():
         for prec in ("fp16", "fp32"):
             mlp[prec] = mlp_bench(torch, R, prec, args.mlp_rays)
             log(f"mlp {prec}: {mlp[prec]}")
+    sweep = sweep_bench(torch, R, w, args.sweep_frames) if args.sweep_frames > 0 else None
+    train = None
+    if args.train_steps > 0:
+        train = train_bench(torch, R, w, args.train_steps, args.train_batch)
+        log(f"train: {train}")
     base = None
     if not args.no_cpu_baseline:
         log(f"timing the FP64 oracle on {args.cpu_sample} rays ...")
@@ -260,6 +327,8 @@ def main():
                      "units_per_launch": round(sum(r16["hits"]) / args.steps, 1),
                      "avg_launch_ms": round(shade_avg_s * 1e3, 4)},
         "mlp": mlp or None,
+        "sweep": sweep,
+        "train": train,
         "cpu_baseline": base,
         "source": source_hash(),
     }

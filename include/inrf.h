@@ -251,6 +251,53 @@ inrf_status inrf_encode(const inrf_model* m, const float* x, int64_t n, float* e
 inrf_status inrf_mlp(const inrf_model* m, int32_t precision, const float* in, int64_t n, float* rgba,
                      void* stream);
 
+/* ------------------------------------------------------------------------
+ * Gradient (training, Sec. 4.2 with the loss of Eq. 8).
+ * ---------------------------------------------------------------------- */
+
+/* Workspace bytes needed by inrf_backward for up to n_rays rays with model m
+ * on the current device (the hit records plus one weight-gradient partial
+ * per resident workgroup); -1 on invalid arguments. */
+int64_t inrf_backward_workspace_size(const inrf_model* m, int64_t n_rays);
+
+/* Adds the gradient of a loss L with respect to the model's parameters,
+ * given d_rgba = dL/d(rgba) (device float32 [n][4], 16-byte aligned) for the
+ * batch of rays ray_o, ray_d (as inrf_forward):
+ *   d_table   device float32 [total slots][INRF_FEATURES], the layout of the
+ *             model's table; gradient w.r.t. the feature of every slot the
+ *             rays read, ADDED in place (FP32 atomic adds: the rounding of
+ *             a slot hit by several rays depends on their order).  NULL skips
+ *             it.  The table itself may be FP32 or FP16; the forward pass is
+ *             recomputed from it.
+ *   d_weights device float32 laid out like the model's weights (W1|W2|W3);
+ *             gradient ADDED in place, deterministic.  NULL skips it.
+ *   rgba      optional device float32 [n][4]: the forward output the
+ *             gradient was taken at (FP32 network), written if set.
+ * The network runs in FP32 (matrix cores) whatever precision inrf_forward
+ * used; a missed ray contributes nothing.  Activations are recomputed, not
+ * read from a previous forward call.  ws: device workspace, 256-byte
+ * aligned, of at least inrf_backward_workspace_size(m, n) bytes. */
+inrf_status inrf_backward(const inrf_model* m, const float* ray_o, const float* ray_d, int64_t n,
+                          const float* d_rgba, float* d_table, float* d_weights, float* rgba, void* ws,
+                          int64_t ws_bytes, void* stream);
+
+/* One Adam step (Kingma and Ba, 2015; the optimiser of Sec. 4.2's training)
+ * over n parameters, in place on device float32 arrays:
+ *   m = beta1 m + (1 - beta1) g,  v = beta2 v + (1 - beta2) g^2,
+ *   param -= lr * (m / (1 - beta1^step)) / (sqrt(v / (1 - beta2^step)) + eps).
+ * With zero_grad set, g is cleared after use.  param_f16 (nullable, device
+ * half [n]) receives the updated parameters rounded to FP16, e.g. the FP16
+ * feature table the reduced-precision render reads. */
+typedef struct inrf_adam_params {
+    float lr, beta1, beta2, eps;
+    int64_t step;      /* t >= 1 */
+    int32_t zero_grad; /* nonzero: clear grad */
+    int32_t pad;
+} inrf_adam_params;
+
+inrf_status inrf_adam(float* param, float* grad, float* m, float* v, int64_t n, const inrf_adam_params* p,
+                      void* param_f16, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,7 +20,7 @@ EXPORTED = [
     "inrf_psh_levels", "inrf_psh_level", "inrf_psh_free", "inrf_build_bvh", "inrf_bvh_get_info",
     "inrf_bvh_copy", "inrf_bvh_free", "inrf_workspace_size", "inrf_render", "inrf_render_profiled",
     "inrf_forward", "inrf_trace",
-    "inrf_encode", "inrf_mlp",
+    "inrf_encode", "inrf_mlp", "inrf_backward_workspace_size", "inrf_backward", "inrf_adam",
 ]
 
 
@@ -62,6 +62,11 @@ class CameraDesc(ctypes.Structure):
                 ("height", c_int32)]
 
 
+class AdamParams(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("step", c_int64), ("zero_grad", c_int32), ("pad", c_int32)]
+
+
 _lib = None
 
 
@@ -91,6 +96,11 @@ def _declare(lib):
         "inrf_trace": (S, [POINTER(ModelDesc), c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
         "inrf_encode": (S, [POINTER(ModelDesc), c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
         "inrf_mlp": (S, [POINTER(ModelDesc), c_int32, c_void_p, c_int64, c_void_p, c_void_p]),
+        "inrf_backward_workspace_size": (c_int64, [POINTER(ModelDesc), c_int64]),
+        "inrf_backward": (S, [POINTER(ModelDesc), c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p,
+                              c_void_p, c_void_p, c_int64, c_void_p]),
+        "inrf_adam": (S, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, POINTER(AdamParams), c_void_p,
+                          c_void_p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -14,7 +14,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libinrf.so")
 ARCH = "gfx950"
 
-SOURCES = ["psh.cpp", "voxel.cpp", "bvh.cpp", "render.hip"]
+SOURCES = ["psh.cpp", "voxel.cpp", "bvh.cpp", "render.hip", "optim.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", f"-I{INCLUDE}", f"-I{CSRC}"]
 # every HIP translation unit: gfx950 only, no packed FP32 instructions
 HIP_FLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

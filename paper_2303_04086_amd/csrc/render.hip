@@ -1,18 +1,19 @@
 // Device entry points of libinrf: closest-hit trace, position encoding, the
 // network alone, and the fused per-ray path (inrf_render / inrf_forward).
 //
-// A frame is three launches on the caller's stream:
-//   k_reset  clears the hit counter in the workspace;
-//   k_trace  one ray per lane: generate (camera) or load (batch) the ray,
-//            closest hit through the BVH with a watertight triangle test,
-//            write depth / triangle / zero colour for misses, and append the
-//            hit record (hit point, unit direction, output index) to a packed
-//            list, one atomic per wave;
-//   k_shade  persistent waves over the packed hits: multi-level PSH gather with
-//            trilinear blend, SH16 of the direction, the MLP on matrix cores,
-//            sigmoid, colour write.
-// Each ray's colour depends only on that ray, so results do not depend on the
-// order in which waves append hits.
+// A frame is four launches on the caller's stream:
+//   k_trace   one ray per lane: generate (camera) or load (batch) the ray,
+//             closest hit through the BVH with a watertight triangle test
+//             (a camera wave traverses as one packet), write depth / triangle
+//             / zero colour for misses, and write the hit records (hit point,
+//             unit direction, output index) of each workgroup in lane order;
+//   k_scan, k_compact  pack the records into one list in workgroup order
+//             (deterministic) and count them;
+//   k_shade   persistent waves over the packed hits: multi-level PSH gather
+//             with trilinear blend, SH16 of the direction, the MLP on matrix
+//             cores, sigmoid, colour write.
+// Each ray's colour depends only on that ray; the packed order fixes which
+// rays share a wave (it matters only to sums over rays, e.g. gradients).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -52,8 +53,8 @@ struct TraceArgs {
     float* rgba;    // nullable
     float* depth;   // nullable
     int32_t* tri;   // nullable
-    HitRec* recs;   // nullable: no records (trace only)
-    int32_t* counter;
+    HitRec* tmp;    // nullable: no records (trace only); else hit records of workgroup b at blk[b].y
+    int2* blk;      // per workgroup: (hit count, first record index in tmp)
 };
 
 // ------------------------------------------------------------- tracing ----
@@ -223,17 +224,96 @@ __device__ void closest_hit(const ModelC& m, const RayPre& R, int* stack, float&
     }
 }
 
+// Closest hit of a wave of camera rays (one shared origin, neighbouring
+// directions) traversed as one packet: the wave walks a single node
+// sequence, visiting a child if any of its active lanes hits it within that
+// lane's current closest distance, so every lane still tests every triangle
+// it could hit and gets the same closest hit as a traversal of its own.
+// Nodes and triangles are read at wave-uniform addresses; the stack of
+// deferred nodes is wave-uniform (`wst`, m.stack_depth entries in LDS).
+// Children are ordered by the entry distance of the lowest lane that hits
+// them.
+__device__ void closest_hit_packet(const ModelC& m, const RayPre& R, bool active, int* wst, float& best_t,
+                                   int32_t& best_i) {
+    best_t = INFINITY;
+    best_i = -1;
+    if (m.n_tris == 0 || __ballot(active) == 0) return;
+    int node = 0, sp = 0;
+    for (int visits = 0; visits < (1 << 20); ++visits) {
+        const float4* p = reinterpret_cast<const float4*>(m.nodes + node);
+        const float4 lx = p[0], ly = p[1], lz = p[2], hx = p[3], hy = p[4], hz = p[5];
+        const int4 ch = *reinterpret_cast<const int4*>(p + 6);
+        const int32_t ref[4] = {ch.x, ch.y, ch.z, ch.w};
+        float tn[4];
+        bool h[4];
+        h[0] = hit_box(R, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, best_t, tn[0]);
+        h[1] = hit_box(R, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, best_t, tn[1]);
+        h[2] = hit_box(R, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, best_t, tn[2]);
+        h[3] = hit_box(R, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, best_t, tn[3]);
+        uint64_t any[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            h[c] = h[c] && active && ref[c] != kBvhEmpty;
+            any[c] = __ballot(h[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (ref[c] < 0 && any[c]) {
+                if (h[c]) leaf(R, m.tris, ref[c], best_t, best_i);
+            }
+        float d[4];
+        int32_t r[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const bool go = ref[c] >= 0 && any[c] != 0;
+            const int rep = go ? int(__builtin_ctzll(any[c])) : 0;
+            d[c] = go ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tn[c]), rep)) : INFINITY;
+            r[c] = go ? ref[c] : kBvhEmpty;
+        }
+#define INRF_CSWAP(a, b)                                     \
+    if (d[b] < d[a]) {                                       \
+        const float td = d[a]; d[a] = d[b]; d[b] = td;       \
+        const int32_t tr = r[a]; r[a] = r[b]; r[b] = tr;     \
+    }
+        INRF_CSWAP(0, 1)
+        INRF_CSWAP(2, 3)
+        INRF_CSWAP(0, 2)
+        INRF_CSWAP(1, 3)
+        INRF_CSWAP(1, 2)
+#undef INRF_CSWAP
+#pragma unroll
+        for (int c = 3; c >= 1; --c)
+            if (r[c] != kBvhEmpty && sp < m.stack_depth) wst[sp++] = r[c];
+        if (r[0] != kBvhEmpty) {
+            node = r[0];
+        } else {
+            if (sp == 0) break;
+            node = __builtin_amdgcn_readfirstlane(wst[--sp]);
+        }
+    }
+}
+
+// One workgroup per 16x16 camera tile (each wave an 8x8 quadrant, so that a
+// packet is compact) or per 256 batch rays.  Writes depth / triangle / zero
+// colour of misses and, if records are requested, the hit records of the
+// workgroup in lane order to tmp[base ..], base = the index of the
+// workgroup's first ray in the output (tiles of a row band are laid out
+// one after another), with blk[b] = (hits, base).
 template <bool CAMERA>
 __global__ __launch_bounds__(kThreads) void k_trace(ModelC m, CamC cam, TraceArgs a) {
-    extern __shared__ int stack[];  // [m.stack_depth][kThreads]
-    int64_t ray;
+    extern __shared__ int stack[];  // batch: [m.stack_depth][kThreads] per-lane stacks
+    __shared__ int wst[(kThreads / 64) * kBvhMaxStack];
+    __shared__ int s_cnt[kThreads / 64];
+    const int lane = __lane_id(), wave = int(threadIdx.x) / 64;
+    int64_t ray, base;
     bool valid;
     float3 o, d;
     if (CAMERA) {
         const int tile = blockIdx.x, tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
-        const int row = ty * kTile + int(threadIdx.x) / kTile, col = tx * kTile + int(threadIdx.x) % kTile;
+        const int row = ty * kTile + 8 * (wave >> 1) + (lane >> 3), col = tx * kTile + 8 * (wave & 1) + (lane & 7);
         valid = row < cam.H && col < cam.W;
         ray = int64_t(row) * cam.W + col;
+        base = int64_t(ty) * kTile * cam.W + int64_t(tx) * kTile * min(kTile, cam.H - ty * kTile);
         const float sx = ((2.f * (float(col) + 0.5f)) / float(cam.W) - 1.f) * cam.tan_x;
         const float sy = (1.f - (2.f * (float(row) + 0.5f)) / float(cam.H)) * cam.tan_y;
         float3 v = make_float3(cam.f[0] + sx * cam.r[0] + sy * cam.u[0], cam.f[1] + sx * cam.r[1] + sy * cam.u[1],
@@ -243,6 +323,7 @@ __global__ __launch_bounds__(kThreads) void k_trace(ModelC m, CamC cam, TraceArg
         o = make_float3(cam.o[0], cam.o[1], cam.o[2]);
     } else {
         ray = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+        base = int64_t(blockIdx.x) * kThreads;
         valid = ray < a.n;
         if (valid) {
             o = make_float3(a.ray_o[3 * ray], a.ray_o[3 * ray + 1], a.ray_o[3 * ray + 2]);
@@ -255,24 +336,32 @@ __global__ __launch_bounds__(kThreads) void k_trace(ModelC m, CamC cam, TraceArg
                         isfinite(d.z) && (d.x != 0.f || d.y != 0.f || d.z != 0.f);
     float t = INFINITY;
     int32_t tri = -1;
-    if (valid && finite) {
+    const bool active = valid && finite;
+    if (CAMERA) {
+        const RayPre R = ray_setup(o, active ? d : make_float3(0.f, 0.f, 1.f));
+        closest_hit_packet(m, R, active, wst + wave * kBvhMaxStack, t, tri);
+    } else if (active) {
         const RayPre R = ray_setup(o, d);
         closest_hit(m, R, stack + threadIdx.x, t, tri);
     }
-    const bool hit = valid && tri >= 0;
+    const bool hit = active && tri >= 0;
     if (valid) {
         if (a.depth) a.depth[ray] = t;
         if (a.tri) a.tri[ray] = tri;
         if (a.rgba && !hit) reinterpret_cast<float4*>(a.rgba)[ray] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    if (a.recs) {
+    if (a.tmp) {
         const uint64_t mask = __ballot(hit);
-        const int lane = __lane_id();
-        int base = 0;
-        if (lane == 0 && mask) base = atomicAdd(a.counter, __popcll(mask));
-        base = __shfl(base, 0);
+        if (lane == 0) s_cnt[wave] = __popcll(mask);
+        __syncthreads();
+        int before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < kThreads / 64; ++w) {
+            before += w < wave ? s_cnt[w] : 0;
+            total += s_cnt[w];
+        }
         if (hit) {
-            const int pos = base + __popcll(mask & ((uint64_t(1) << lane) - 1));
+            const int64_t pos = base + before + __popcll(mask & ((uint64_t(1) << lane) - 1));
             const float inv = 1.f / sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
             HitRec h;
             h.x = clamp01(o.x + t * d.x);
@@ -283,13 +372,50 @@ __global__ __launch_bounds__(kThreads) void k_trace(ModelC m, CamC cam, TraceArg
             h.dy = d.y * inv;
             h.dz = d.z * inv;
             h.pad = 0;
-            a.recs[pos] = h;
+            a.tmp[pos] = h;
         }
+        if (threadIdx.x == 0) a.blk[blockIdx.x] = make_int2(total, int(base));
     }
 }
 
-__global__ void k_reset(int32_t* counter) {
-    if (threadIdx.x == 0) *counter = 0;
+// Exclusive prefix sum of the workgroups' hit counts (one workgroup of
+// 1024 threads, each summing a contiguous run), and the total into *counter.
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void k_scan(const int2* __restrict__ blk, int n_blk,
+                                                       int32_t* __restrict__ offsets, int32_t* __restrict__ counter) {
+    __shared__ int s[kScanThreads];
+    const int per = (n_blk + kScanThreads - 1) / kScanThreads;
+    const int lo = min(n_blk, int(threadIdx.x) * per), hi = min(n_blk, lo + per);
+    int sum = 0;
+    for (int i = lo; i < hi; ++i) sum += blk[i].x;
+    s[threadIdx.x] = sum;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {  // inclusive Hillis-Steele scan
+        const int v = threadIdx.x >= unsigned(off) ? s[threadIdx.x - off] : 0;
+        __syncthreads();
+        s[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int run = s[threadIdx.x] - sum;
+    for (int i = lo; i < hi; ++i) {
+        offsets[i] = run;
+        run += blk[i].x;
+    }
+    if (threadIdx.x == kScanThreads - 1) *counter = s[kScanThreads - 1];
+}
+
+// Packs the workgroups' records into one list in workgroup order (tile
+// raster order for a camera), so the list does not depend on timing.
+__global__ __launch_bounds__(kThreads) void k_compact(const int2* __restrict__ blk, const int32_t* __restrict__ offsets,
+                                                      const HitRec* __restrict__ tmp, HitRec* __restrict__ recs) {
+    const int2 b = blk[blockIdx.x];
+    const int32_t off = offsets[blockIdx.x];
+    for (int i = threadIdx.x; i < b.x; i += kThreads) {
+        const float4* src = reinterpret_cast<const float4*>(tmp + b.y + i);
+        float4* dst = reinterpret_cast<float4*>(recs + off + i);
+        dst[0] = src[0];
+        dst[1] = src[1];
+    }
 }
 
 // ------------------------------------------------------------- shading ----
@@ -407,66 +533,65 @@ __global__ __launch_bounds__(kThreads) void k_encode(ModelC m, const float* __re
     }
 }
 
-// The network alone on caller inputs [n][d_in] in natural order: each
-// 16-ray block is staged through the wave's LDS tile like k_shade's.
+// The network alone on caller inputs [n][d_in] in natural order: lane
+// (g, r) loads exactly its B operands of ray r straight from memory.
 template <class P, int LPG>
 __global__ __launch_bounds__(kThreads) void k_mlp(ModelC m, const float* __restrict__ x, int64_t n,
                                                   float* __restrict__ rgba) {
     typedef Mfma<P> M;
     typedef typename M::vec Vec;
     typedef ShadeShape<P, LPG> S;
-    typedef typename TileElem<P>::type T;
     extern __shared__ float4 lds_v[];
     Vec* W = reinterpret_cast<Vec*>(lds_v);
     stage_weights<P>(m.weights, m.n_levels, S::F, W);
-    T* tile = reinterpret_cast<T*>(reinterpret_cast<char*>(lds_v) + weight_bytes(S::F, S::V) +
-                                   (threadIdx.x / 64) * S::tile_bytes);
     __syncthreads();
-    const int d_in = 2 * m.n_levels + INRF_SH_DIM;
-    const int lane = __lane_id(), r = lane & 15;
+    const int L2 = 2 * m.n_levels, d_in = L2 + INRF_SH_DIM;
+    const int lane = __lane_id(), g = lane >> 4, r = lane & 15;
     for (int64_t blk = int64_t(blockIdx.x) * (kThreads / 64) + threadIdx.x / 64; blk * 16 < n;
          blk += int64_t(gridDim.x) * (kThreads / 64)) {
-        // rows of the tile: 16 rays x F feature slots, 4 lanes per row
-        for (int k = lane; k < 16 * S::F; k += 64) {
-            const int row = k / S::F, slot = k % S::F;
-            const int64_t ray = blk * 16 + row;
-            tile[row * S::STRIDE + slot] = T((ray < n && slot < 2 * m.n_levels) ? x[ray * d_in + slot] : 0.f);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const int64_t ray = blk * 16 + r;
         const bool act = ray < n;
-        // the SH inputs are given, not computed: rebuild them from the caller's values
+        const float* row = x + (act ? ray : 0) * d_in;
         Vec b1[S::S1];
-        load_inputs<P, S::F>(tile + r * S::STRIDE, 0.f, 0.f, 1.f, b1);
-        {
-            const int g = lane >> 4;
-            float shv[16];
+        if constexpr (S::V == 1) {
 #pragma unroll
-            for (int k = 0; k < 16; ++k) shv[k] = act ? x[ray * d_in + 2 * m.n_levels + k] : 0.f;
-            if constexpr (S::V == 1) {
+            for (int j = 0; j < S::F / 16; ++j)
 #pragma unroll
-                for (int t = 0; t < 4; ++t)
-                    b1[S::F / 4 + t] = g == 0 ? shv[t] : (g == 1 ? shv[4 + t] : (g == 2 ? shv[8 + t] : shv[12 + t]));
-            } else {
+                for (int t = 0; t < 4; ++t) {
+                    const int k = 16 * j + 4 * g + t;
+                    b1[4 * j + t] = (act && k < L2) ? row[k] : 0.f;
+                }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) b1[S::F / 4 + t] = act ? row[L2 + 4 * g + t] : 0.f;
+        } else {
+#pragma unroll
+            for (int c = 0; c < S::F / 32; ++c) {
                 Vec v;
 #pragma unroll
-                for (int t = 0; t < 8; ++t) v[t] = M::cvt(g == 0 ? shv[t] : (g == 1 ? shv[8 + t] : 0.f));
-                b1[S::S1 - 1] = v;
+                for (int t = 0; t < 8; ++t) {
+                    const int k = 32 * c + 8 * g + t;
+                    v[t] = M::cvt((act && k < L2) ? row[k] : 0.f);
+                }
+                b1[c] = v;
             }
+            Vec v;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) v[t] = M::cvt((act && g < 2) ? row[L2 + 8 * g + t] : 0.f);
+            b1[S::S1 - 1] = v;
         }
         const f32x4 o = mlp_block<P, S::F>(W, b1);
-        if ((lane >> 4) == 0 && act)
+        if (g == 0 && act)
             reinterpret_cast<float4*>(rgba)[ray] =
                 make_float4(sigmoidf(o[0]), sigmoidf(o[1]), sigmoidf(o[2]), sigmoidf(o[3]));
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
 }  // namespace dev
+}  // namespace inrf
+
+#include "backward_device.hpp"
+
+namespace inrf {
 
 // ------------------------------------------------------------ host side ---
 namespace {
@@ -474,6 +599,28 @@ namespace {
 using namespace dev;
 
 constexpr int64_t kWsHeader = 256;
+
+int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
+
+// Workspace of a trace of up to n rays: counter | records | per-workgroup
+// records | per-workgroup (count, base) | per-workgroup offsets.  A camera
+// of W x H = n pixels has at most ceil(W/16) ceil(H/16) <= n/8 + 2 tiles.
+struct WsLayout {
+    int64_t recs, tmp, blk, offsets, end;
+    explicit WsLayout(int64_t n) {
+        const int64_t nb = n / 8 + 2;
+        recs = kWsHeader;
+        tmp = align256(recs + n * int64_t(sizeof(HitRec)));
+        blk = align256(tmp + n * int64_t(sizeof(HitRec)));
+        offsets = align256(blk + nb * int64_t(sizeof(int2)));
+        end = align256(offsets + nb * int64_t(sizeof(int32_t)));
+    }
+};
+
+template <class T>
+T* ws_at(void* ws, int64_t off) {
+    return reinterpret_cast<T*>(reinterpret_cast<char*>(ws) + off);
+}
 
 void check_hip(hipError_t e, const char* what) {
     if (e != hipSuccess) fail(INRF_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
@@ -563,7 +710,7 @@ void launch_shade_t(const ModelC& c, const HitRec* recs, const int32_t* counter,
 
 template <class P, int LPG>
 void launch_mlp_t(const ModelC& c, const float* in, int64_t n, float* rgba, hipStream_t s) {
-    const size_t lds = ShadeShape<P, LPG>::lds_bytes;
+    const size_t lds = size_t(weight_bytes(ShadeShape<P, LPG>::F, ShadeShape<P, LPG>::V));
     auto kern = k_mlp<P, LPG>;
     allow_lds(kern, lds);
     const int64_t blocks = (n + kThreads / 4 - 1) / (kThreads / 4);  // 16 rays per wave step
@@ -606,6 +753,37 @@ void record(void* const* events, int i, hipStream_t s) {
     if (events && events[i]) check_hip(hipEventRecord(reinterpret_cast<hipEvent_t>(events[i]), s), "hipEventRecord");
 }
 
+// Clears the hit counter, then traces n rays (camera rays when cam is set),
+// writing depth / triangle / zero colour of misses and appending hit records.
+// Traces n rays (camera rays when cam is set), writing depth / triangle /
+// zero colour of misses, then packs the hit records into one list in
+// workgroup order and writes its length to the counter.
+void trace_to_hits(const ModelC& c, const CamC* cam, const float* ray_o, const float* ray_d, int64_t n, float* rgba,
+                   float* depth, int32_t* tri, void* ws, hipStream_t s) {
+    const WsLayout L(n);
+    int32_t* counter = ws_at<int32_t>(ws, 0);
+    HitRec* recs = ws_at<HitRec>(ws, L.recs);
+    int2* blk = ws_at<int2>(ws, L.blk);
+    int32_t* offsets = ws_at<int32_t>(ws, L.offsets);
+    TraceArgs a{ray_o, ray_d, n, rgba, depth, tri, ws_at<HitRec>(ws, L.tmp), blk};
+    int n_blk;
+    if (cam) {
+        n_blk = cam->tiles_x * ((cam->H + kTile - 1) / kTile);
+        hipLaunchKernelGGL(k_trace<true>, dim3(n_blk), dim3(kThreads), 0, s, c, *cam, a);
+    } else {
+        CamC none;
+        std::memset(&none, 0, sizeof(none));
+        n_blk = int((n + kThreads - 1) / kThreads);
+        const size_t stack_bytes = size_t(c.stack_depth) * kThreads * sizeof(int);
+        hipLaunchKernelGGL(k_trace<false>, dim3(n_blk), dim3(kThreads), stack_bytes, s, c, none, a);
+    }
+    launch_check("k_trace");
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, blk, n_blk, offsets, counter);
+    launch_check("k_scan");
+    hipLaunchKernelGGL(k_compact, dim3(n_blk), dim3(kThreads), 0, s, blk, offsets, a.tmp, recs);
+    launch_check("k_compact");
+}
+
 void run_path(const inrf_model* m, int32_t precision, const CamC* cam, const float* ray_o, const float* ray_d,
               int64_t n, float* rgba, float* depth, int32_t* tri, void* ws, int64_t ws_bytes, void* stream,
               void* const* events = nullptr) {
@@ -621,28 +799,87 @@ void run_path(const inrf_model* m, int32_t precision, const CamC* cam, const flo
         fail(INRF_E_SIZE, "workspace of " + std::to_string(ws_bytes) + " bytes < " +
                               std::to_string(inrf_workspace_size(n)) + " needed");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    int32_t* counter = reinterpret_cast<int32_t*>(ws);
-    HitRec* recs = reinterpret_cast<HitRec*>(reinterpret_cast<char*>(ws) + kWsHeader);
+    const int32_t* counter = ws_at<int32_t>(ws, 0);
+    const HitRec* recs = ws_at<HitRec>(ws, WsLayout(n).recs);
     record(events, 0, s);
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, counter);
-    launch_check("k_reset");
-    TraceArgs a{ray_o, ray_d, n, rgba, depth, tri, recs, counter};
-    const size_t stack_bytes = size_t(c.stack_depth) * kThreads * sizeof(int);
-    if (cam) {
-        const int tiles = cam->tiles_x * ((cam->H + kTile - 1) / kTile);
-        hipLaunchKernelGGL(k_trace<true>, dim3(tiles), dim3(kThreads), stack_bytes, s, c, *cam, a);
-    } else {
-        CamC none;
-        std::memset(&none, 0, sizeof(none));
-        hipLaunchKernelGGL(k_trace<false>, dim3(unsigned((n + kThreads - 1) / kThreads)), dim3(kThreads),
-                           stack_bytes, s, c, none, a);
-    }
-    launch_check("k_trace");
+    trace_to_hits(c, cam, ray_o, ray_d, n, rgba, depth, tri, ws, s);
     record(events, 1, s);
     if (c.table_dtype == INRF_F32) launch_shade<float>(c, precision, recs, counter, rgba, s);
     else launch_shade<__half>(c, precision, recs, counter, rgba, s);
     launch_check("k_shade");
     record(events, 2, s);
+}
+
+// ---- gradient (k_backward)
+
+// Workgroups of the backward launch (one weight-gradient partial each): as
+// many as the device keeps resident.
+template <class TableT, int LPG>
+unsigned backward_grid_t() {
+    const size_t lds = BackShape<LPG>::lds_bytes;
+    auto kern = k_backward<TableT, LPG>;
+    allow_lds(kern, lds);
+    return resident_grid(kern, lds);
+}
+
+unsigned backward_grid(const ModelC& c) {
+    unsigned g = 0;
+#define INRF_BGRID(LPG) \
+    g = c.table_dtype == INRF_F32 ? backward_grid_t<float, LPG>() : backward_grid_t<__half, LPG>()
+    INRF_LPG_SWITCH(c.n_levels, INRF_BGRID)
+#undef INRF_BGRID
+    return g;
+}
+
+int64_t backward_ws_bytes(const ModelC& c, int64_t n) {
+    return WsLayout(n).end + int64_t(backward_grid(c)) * weight_count(c.n_levels) * int64_t(sizeof(float));
+}
+
+template <class TableT, int LPG>
+void launch_backward_t(const ModelC& c, unsigned grid, const HitRec* recs, const int32_t* counter,
+                       const float* d_rgba, float* d_table, float* partial, float* rgba, hipStream_t s) {
+    const size_t lds = BackShape<LPG>::lds_bytes;
+    hipLaunchKernelGGL((k_backward<TableT, LPG>), dim3(grid), dim3(kThreads), lds, s, c, recs, counter, d_rgba,
+                       d_table, partial, rgba);
+}
+
+void run_backward(const inrf_model* m, const float* ray_o, const float* ray_d, int64_t n, const float* d_rgba,
+                  float* d_table, float* d_weights, float* rgba, void* ws, int64_t ws_bytes, void* stream) {
+    const ModelC c = make_model(m, true, true);
+    require(m->weights != nullptr, "weights must be set");
+    require(n >= 0 && n <= (int64_t(1) << 31) - 1, "n must be in [0, 2^31)");
+    if (n == 0) return;
+    require(ray_o && ray_d && d_rgba, "ray and gradient buffers must be set");
+    require(ws != nullptr, "workspace is NULL");
+    require((reinterpret_cast<uintptr_t>(ws) & 255) == 0, "workspace must be 256-byte aligned");
+    require((reinterpret_cast<uintptr_t>(d_rgba) & 15) == 0 && (reinterpret_cast<uintptr_t>(rgba) & 15) == 0,
+            "d_rgba and rgba must be 16-byte aligned");
+    require((reinterpret_cast<uintptr_t>(d_table) & 7) == 0, "d_table must be 8-byte aligned");
+    const unsigned grid = backward_grid(c);
+    const int64_t need = backward_ws_bytes(c, n);
+    if (ws_bytes < need)
+        fail(INRF_E_SIZE,
+             "workspace of " + std::to_string(ws_bytes) + " bytes < " + std::to_string(need) + " needed");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int32_t* counter = ws_at<int32_t>(ws, 0);
+    const HitRec* recs = ws_at<HitRec>(ws, WsLayout(n).recs);
+    float* partial = ws_at<float>(ws, WsLayout(n).end);
+    trace_to_hits(c, nullptr, ray_o, ray_d, n, rgba, nullptr, nullptr, ws, s);
+#define INRF_BACK(LPG)                                                                                   \
+    do {                                                                                                \
+        if (c.table_dtype == INRF_F32)                                                                  \
+            launch_backward_t<float, LPG>(c, grid, recs, counter, d_rgba, d_table, partial, rgba, s);  \
+        else launch_backward_t<__half, LPG>(c, grid, recs, counter, d_rgba, d_table, partial, rgba, s); \
+    } while (0)
+    INRF_LPG_SWITCH(c.n_levels, INRF_BACK)
+#undef INRF_BACK
+    launch_check("k_backward");
+    if (d_weights) {
+        const int nw = weight_count(c.n_levels);
+        hipLaunchKernelGGL(k_reduce_partials, dim3((nw + 255) / 256), dim3(256), 0, s, partial, int(grid), nw,
+                           d_weights);
+        launch_check("k_reduce_partials");
+    }
 }
 
 CamC make_camera(const inrf_camera* cam) {
@@ -674,7 +911,7 @@ extern "C" {
 
 int64_t inrf_workspace_size(int64_t n_rays) {
     if (n_rays < 0) return -1;
-    return kWsHeader + n_rays * int64_t(sizeof(dev::HitRec));
+    return WsLayout(n_rays).end;
 }
 
 inrf_status inrf_render(const inrf_model* m, int32_t precision, const inrf_camera* cam, float* rgba, float* depth,
@@ -704,6 +941,22 @@ inrf_status inrf_forward(const inrf_model* m, int32_t precision, const float* ra
     });
 }
 
+int64_t inrf_backward_workspace_size(const inrf_model* m, int64_t n_rays) {
+    int64_t out = -1;
+    const inrf_status st = guarded("inrf_backward_workspace_size", [&] {
+        require(n_rays >= 0, "n_rays must be >= 0");
+        out = backward_ws_bytes(make_model(m, false, false), n_rays);
+    });
+    return st == INRF_OK ? out : -1;
+}
+
+inrf_status inrf_backward(const inrf_model* m, const float* ray_o, const float* ray_d, int64_t n, const float* d_rgba,
+                          float* d_table, float* d_weights, float* rgba, void* ws, int64_t ws_bytes, void* stream) {
+    return guarded("inrf_backward", [&] {
+        run_backward(m, ray_o, ray_d, n, d_rgba, d_table, d_weights, rgba, ws, ws_bytes, stream);
+    });
+}
+
 inrf_status inrf_trace(const inrf_model* m, const float* ray_o, const float* ray_d, int64_t n, int32_t* tri,
                        float* t, void* stream) {
     return guarded("inrf_trace", [&] {
@@ -711,7 +964,7 @@ inrf_status inrf_trace(const inrf_model* m, const float* ray_o, const float* ray
         require(n >= 0 && n <= (int64_t(1) << 31) - 1, "n must be in [0, 2^31)");
         require(n == 0 || (ray_o && ray_d && tri && t), "NULL buffer");
         if (n == 0) return;
-        dev::TraceArgs a{ray_o, ray_d, n, nullptr, t, tri, nullptr, nullptr};
+        dev::TraceArgs a{ray_o, ray_d, n, nullptr, t, tri, nullptr, nullptr};  // no records
         dev::CamC none;
         std::memset(&none, 0, sizeof(none));
         const size_t stack_bytes = size_t(c.stack_depth) * dev::kThreads * sizeof(int);

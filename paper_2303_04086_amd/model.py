@@ -270,3 +270,50 @@ class Renderer:
         L.check(L.lib().inrf_mlp(ctypes.byref(self.desc(next(iter(self.tables)))), PRECISIONS[precision],
                                  L.ptr(inputs), n, L.ptr(out), self._stream(stream)))
         return out
+
+    # -- gradient ------------------------------------------------------------
+    def backward_workspace(self, n_rays: int, table: str = "f32"):
+        need = int(L.lib().inrf_backward_workspace_size(ctypes.byref(self.desc(table)), n_rays))
+        if need < 0:
+            L.check(-1)
+        if getattr(self, "_bws", None) is None or self._bws.numel() < need:
+            self._bws = self.torch.empty(need, dtype=self.torch.uint8, device=self.device)
+        return self._bws
+
+    def backward(self, o, d, d_rgba, table="f32", d_table=None, d_weights=None, rgba=None, stream=None):
+        """Adds dL/d(table) to d_table (float32, shaped like the table) and
+        dL/d(weights) to d_weights (float32, shaped like the flat weights),
+        given d_rgba = dL/d(rgba) for the rays o, d; either may be None.
+        `rgba`, if given, receives the forward output (FP32 network)."""
+        o = o.contiguous()
+        d = d.contiguous()
+        d_rgba = d_rgba.contiguous()
+        n = o.shape[0]
+        for name, t, shape in (("d_table", d_table, (self.n_slots, L.FEATURES)),
+                               ("d_weights", d_weights, tuple(self.weights.shape)),
+                               ("rgba", rgba, (n, 4)), ("d_rgba", d_rgba, (n, 4))):
+            if t is not None and (tuple(t.shape) != shape or t.dtype != self.torch.float32 or not t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous float32 tensor of shape {shape}")
+        ws = self.backward_workspace(n, table)
+        L.check(L.lib().inrf_backward(ctypes.byref(self.desc(table)), L.ptr(o), L.ptr(d), n, L.ptr(d_rgba),
+                                      L.ptr(d_table), L.ptr(d_weights), L.ptr(rgba), L.ptr(ws), ws.numel(),
+                                      self._stream(stream)))
+
+
+def adam_step(param, grad, m, v, step: int, lr: float = 1e-2, beta1: float = 0.9, beta2: float = 0.99,
+              eps: float = 1e-15, zero_grad: bool = True, param_f16=None, stream=None):
+    """One Adam step in place on contiguous float32 device tensors of equal
+    size (the library's k_adam); param_f16, if given, receives the updated
+    parameters in FP16."""
+    import torch
+    n = param.numel()
+    for t in (grad, m, v):
+        if t.numel() != n or t.dtype != torch.float32 or not t.is_contiguous():
+            raise ValueError("grad, m, v must be contiguous float32 tensors of param's size")
+    if param_f16 is not None and (param_f16.numel() != n or param_f16.dtype != torch.float16):
+        raise ValueError("param_f16 must be a float16 tensor of param's size")
+    p = L.AdamParams()
+    p.lr, p.beta1, p.beta2, p.eps, p.step, p.zero_grad = lr, beta1, beta2, eps, int(step), int(bool(zero_grad))
+    s = stream if stream is not None else torch.cuda.current_stream(param.device)
+    L.check(L.lib().inrf_adam(L.ptr(param), L.ptr(grad), L.ptr(m), L.ptr(v), n, ctypes.byref(p), L.ptr(param_f16),
+                              ctypes.c_void_p(s.cuda_stream)))

@@ -20,6 +20,19 @@ def random_rays(n: int, seed: int, distance: float = 2.0, spread: float = 0.35,
     return o.astype(np.float32), d.astype(np.float32)
 
 
+def view_rays(origins, n: int, seed: int, spread: float = 0.73, center=(0.5, 0.5, 0.5)):
+    """Training batches: each ray starts at one of `origins` (float [k, 3],
+    e.g. camera positions), chosen uniformly, and aims at `center` plus a
+    uniform offset of up to `spread` per axis (0.73 covers a 40-degree view
+    of the unit cube from distance 2).  float32 [n, 3] each, unit dirs."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    org = np.asarray(origins, np.float64).reshape(-1, 3)
+    o = org[rng.integers(0, len(org), size=n)]
+    d = np.asarray(center, np.float64) + rng.uniform(-spread, spread, size=(n, 3)) - o
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    return o.astype(np.float32), d.astype(np.float32)
+
+
 def surface_points(verts: np.ndarray, tris: np.ndarray, n: int, seed: int) -> np.ndarray:
     """Uniform barycentric samples on uniformly chosen triangles, float32 [n, 3]."""
     rng = np.random.Generator(np.random.PCG64(seed))

@@ -82,3 +82,23 @@ def test_sigmoid_slope_at_zero():
     g = oracle.backward_rays(m, o, d, gy)
     assert np.all(g["weights"][0] == 0) and np.all(g["weights"][1] == 0) and np.all(g["weights"][2] == 0)
     assert all(len(f) == 0 or all(np.all(v == 0) for v in f.values()) for f in g["features"])
+
+
+def test_adam_first_step_is_normalised_gradient():
+    rng = np.random.default_rng(5)
+    p, g = rng.normal(size=1000), rng.normal(size=1000)
+    g[:10] = 0.0
+    lr, eps = 1e-2, 1e-15
+    p1, m1, v1 = oracle.adam_step(p, g, np.zeros_like(p), np.zeros_like(p), 1, lr, 0.9, 0.99, eps)
+    assert np.allclose(p1 - p, -lr * g / (np.abs(g) + eps), rtol=1e-12, atol=0)
+    assert np.array_equal(p1[:10], p[:10])
+    assert np.allclose(m1, 0.1 * g) and np.allclose(v1, 0.01 * g * g)
+
+
+def test_adam_constant_gradient_keeps_step():
+    g = np.array([0.3, -2.0, 1e-3])
+    p, m, v = np.zeros(3), np.zeros(3), np.zeros(3)
+    for t in range(1, 30):
+        q, m, v = oracle.adam_step(p, g, m, v, t, 0.05, 0.9, 0.99, 1e-12)
+        assert np.allclose(q - p, -0.05 * g / (np.abs(g) + 1e-12), rtol=1e-9)
+        p = q
