@@ -533,11 +533,23 @@ __global__ __launch_bounds__(kThreads) void k_encode(ModelC m, const float* __re
     }
 }
 
+// a[k .. k+3] with entries at index >= limit read as zero (and all zero for
+// an inactive lane); one 16-byte load when the four lie below the limit and
+// `vec` says that a + k is 16-byte aligned.
+__device__ __forceinline__ f32x4 load_inputs4(const float* a, int k, int limit, bool act, bool vec) {
+    if (!act || k >= limit) return f32x4{0.f, 0.f, 0.f, 0.f};
+    if (vec && k + 4 <= limit) return *reinterpret_cast<const f32x4*>(a + k);
+    f32x4 v;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) v[t] = k + t < limit ? a[k + t] : 0.f;
+    return v;
+}
+
 // The network alone on caller inputs [n][d_in] in natural order: lane
 // (g, r) loads exactly its B operands of ray r straight from memory.
 template <class P, int LPG>
 __global__ __launch_bounds__(kThreads) void k_mlp(ModelC m, const float* __restrict__ x, int64_t n,
-                                                  float* __restrict__ rgba) {
+                                                  float* __restrict__ rgba, bool vec) {
     typedef Mfma<P> M;
     typedef typename M::vec Vec;
     typedef ShadeShape<P, LPG> S;
@@ -555,28 +567,35 @@ __global__ __launch_bounds__(kThreads) void k_mlp(ModelC m, const float* __restr
         Vec b1[S::S1];
         if constexpr (S::V == 1) {
 #pragma unroll
-            for (int j = 0; j < S::F / 16; ++j)
+            for (int j = 0; j < S::F / 16; ++j) {
+                const f32x4 v = load_inputs4(row, 16 * j + 4 * g, L2, act, vec);
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int k = 16 * j + 4 * g + t;
-                    b1[4 * j + t] = (act && k < L2) ? row[k] : 0.f;
-                }
+                for (int t = 0; t < 4; ++t) b1[4 * j + t] = v[t];
+            }
+            const f32x4 v = load_inputs4(row + L2, 4 * g, INRF_SH_DIM, act, vec);
 #pragma unroll
-            for (int t = 0; t < 4; ++t) b1[S::F / 4 + t] = act ? row[L2 + 4 * g + t] : 0.f;
+            for (int t = 0; t < 4; ++t) b1[S::F / 4 + t] = v[t];
         } else {
 #pragma unroll
             for (int c = 0; c < S::F / 32; ++c) {
+                const f32x4 lo = load_inputs4(row, 32 * c + 8 * g, L2, act, vec);
+                const f32x4 hi = load_inputs4(row, 32 * c + 8 * g + 4, L2, act, vec);
                 Vec v;
 #pragma unroll
-                for (int t = 0; t < 8; ++t) {
-                    const int k = 32 * c + 8 * g + t;
-                    v[t] = M::cvt((act && k < L2) ? row[k] : 0.f);
+                for (int t = 0; t < 4; ++t) {
+                    v[t] = M::cvt(lo[t]);
+                    v[4 + t] = M::cvt(hi[t]);
                 }
                 b1[c] = v;
             }
+            const f32x4 lo = load_inputs4(row + L2, 8 * g, g < 2 ? INRF_SH_DIM : 0, act, vec);
+            const f32x4 hi = load_inputs4(row + L2, 8 * g + 4, g < 2 ? INRF_SH_DIM : 0, act, vec);
             Vec v;
 #pragma unroll
-            for (int t = 0; t < 8; ++t) v[t] = M::cvt((act && g < 2) ? row[L2 + 8 * g + t] : 0.f);
+            for (int t = 0; t < 4; ++t) {
+                v[t] = M::cvt(lo[t]);
+                v[4 + t] = M::cvt(hi[t]);
+            }
             b1[S::S1 - 1] = v;
         }
         const f32x4 o = mlp_block<P, S::F>(W, b1);
@@ -715,7 +734,9 @@ void launch_mlp_t(const ModelC& c, const float* in, int64_t n, float* rgba, hipS
     allow_lds(kern, lds);
     const int64_t blocks = (n + kThreads / 4 - 1) / (kThreads / 4);  // 16 rays per wave step
     const unsigned grid = unsigned(std::min<int64_t>(blocks, resident_grid(kern, lds)));
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, c, in, n, rgba);
+    // rows start 16-byte aligned when the input array does and d_in = 2L + 16 is a multiple of 4
+    const bool vec = (reinterpret_cast<uintptr_t>(in) & 15) == 0 && (c.n_levels % 2) == 0;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, c, in, n, rgba, vec);
 }
 
 // Levels per lane group (ceil(L / 4)) selects the instantiation.

@@ -113,6 +113,26 @@ def test_mlp_precisions(tiny, R, R16, n, levels):
     assert np.abs(got - oracle.mlp_forward(loud, tiny.weights)).max() <= 1e-5
 
 
+@pytest.mark.parametrize("n_levels", [5, 13])
+def test_mlp_odd_levels_and_unaligned_inputs(n_levels):
+    """Rows that are not 16-byte aligned (odd level count, or an input array
+    starting 4 bytes into an allocation) take the element-wise load path."""
+    w = synth.workload_tiny()
+    w.res = list(range(4, 4 + n_levels))
+    w.weights = synth.xavier_mlp(5, w.d_in)
+    R5 = make_renderer(w, tables=("f32",))
+    rng = np.random.default_rng(n_levels)
+    n = 999
+    inp = np.concatenate([rng.uniform(-1, 1, (n, w.d_in - 16)), oracle.sh_real(rng.normal(size=(n, 3)))], 1)
+    want = oracle.mlp_forward(inp, w.weights)
+    flat = torch.zeros(n * w.d_in + 1, device="cuda")
+    flat[1:] = _dev(inp.astype(np.float32).reshape(-1))
+    for x in (_dev(inp.astype(np.float32)), flat[1:].view(n, w.d_in)):
+        for prec, tol in (("fp32", 1e-5), ("fp16", 2e-3)):
+            got = R5.mlp(x, prec).cpu().numpy()
+            assert np.abs(got - want).max() <= tol, (prec, x.data_ptr() % 16)
+
+
 def test_render_full_frame_fp32(tiny, R, tiny_oracle):
     cam = tiny.cameras[0]
     depth = torch.empty(cam.height * cam.width, device="cuda")
