@@ -222,6 +222,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--distance", type=float, default=2.0,
+                    help="camera distance from the object centre (the headline workload uses 2.0)")
     ap.add_argument("--width", type=int, default=3840)
     ap.add_argument("--height", type=int, default=2160)
     ap.add_argument("--cpu-sample", type=int, default=1024)
@@ -259,6 +261,9 @@ def main():
 
     W, H = args.width, args.height
     w = synth.workload_object(W, H)
+    if args.distance != 2.0:
+        w.cameras = synth.fibonacci_cameras(8, args.distance, W, H)
+        w.name += f"_d{args.distance}"
     log(f"workload {w.name}: {len(w.tris)} triangles, levels {w.res}")
     t0 = time.time()
     levels = P.build_psh(w.verts, w.tris, w.res, dilate=w.dilate, seed=w.psh_seed)

@@ -145,6 +145,22 @@ inrf_status inrf_psh_level(const inrf_psh* psh, int32_t level, inrf_psh_level_in
 
 void inrf_psh_free(inrf_psh* psh);
 
+/* Device storage order of a level's two cubes (the hash table H of side mbar
+ * and the offset table Phi of side rbar).  Cells are stored in bricks of
+ * 8 x 4 x 1 cells (32 entries, one 128-byte line of 4-byte entries), x
+ * fastest inside a brick and across bricks, each z plane padded to whole
+ * bricks:
+ *   index(x, y, z) = z * P + (y/4) * R + (x/8) * 32 + (y%4) * 8 + x%8,
+ *   R = 32 * ceil(side/8), P = R * ceil(side/4),
+ * so the eight corners of a cell span 2.8 lines on average instead of 4.1.
+ * The slot of Eq. 1 is unchanged; only where it is stored differs.
+ * inrf_brick_entries: entries one level's cube occupies (P * side), -1 if
+ * side is not in [1, 1024].  inrf_brick_index: storage index of each linear
+ * cell index (z*side + y)*side + x (host arrays of n; INRF_E_INVALID if one
+ * is out of range, then nothing is written). */
+int64_t inrf_brick_entries(int32_t side);
+inrf_status inrf_brick_index(int32_t side, const int64_t* linear, int64_t n, int64_t* out);
+
 typedef struct inrf_bvh inrf_bvh; /* opaque host object */
 
 typedef struct inrf_bvh_info {
@@ -176,17 +192,19 @@ void inrf_bvh_free(inrf_bvh* bvh);
 
 typedef struct inrf_level_desc {
     int32_t res, mbar, rbar, pad;
-    int64_t phi_offset;  /* first entry of this level in `phi` */
-    int64_t slot_offset; /* first slot of this level in `table` */
+    int64_t phi_offset;  /* first entry of this level in `phi` (inrf_brick_entries(rbar) entries) */
+    int64_t slot_offset; /* first entry of this level in `table` (inrf_brick_entries(mbar) entries) */
 } inrf_level_desc;
 
 typedef struct inrf_model {
     int32_t n_levels;    /* L, 1..INRF_MAX_LEVELS */
     int32_t table_dtype; /* INRF_F32 or INRF_F16 */
     inrf_level_desc levels[INRF_MAX_LEVELS];
-    const uint32_t* phi;    /* device, packed offsets of all levels */
-    const void* table;      /* device, [total slots][INRF_FEATURES] of table_dtype;
-                               slots of unoccupied vertices hold zeros */
+    const uint32_t* phi;    /* device, packed offsets of all levels, each level's cube
+                               in the brick order of inrf_brick_index */
+    const void* table;      /* device, [total entries][INRF_FEATURES] of table_dtype,
+                               each level's cube in brick order; slots of unoccupied
+                               vertices and padding hold zeros */
     const float* weights;   /* device FP32 W1 [64][d_in] | W2 [64][64] | W3 [4][64],
                                row-major [out][in], d_in = 2*L + 16; the FP16 and
                                BF16 precisions round them on the fly */

@@ -17,7 +17,8 @@ MAX_LEVELS, FEATURES, SH_DIM, HIDDEN, OUT = 32, 2, 16, 64, 4
 
 EXPORTED = [
     "inrf_last_error", "inrf_version", "inrf_psh_params_default", "inrf_build_psh", "inrf_build_psh_keys",
-    "inrf_psh_levels", "inrf_psh_level", "inrf_psh_free", "inrf_build_bvh", "inrf_bvh_get_info",
+    "inrf_psh_levels", "inrf_psh_level", "inrf_psh_free", "inrf_brick_entries", "inrf_brick_index",
+    "inrf_build_bvh", "inrf_bvh_get_info",
     "inrf_bvh_copy", "inrf_bvh_free", "inrf_workspace_size", "inrf_render", "inrf_render_profiled",
     "inrf_forward", "inrf_trace",
     "inrf_encode", "inrf_mlp", "inrf_backward_workspace_size", "inrf_backward", "inrf_adam",
@@ -82,6 +83,8 @@ def _declare(lib):
         "inrf_psh_levels": (c_int32, [c_void_p]),
         "inrf_psh_level": (S, [c_void_p, c_int32, POINTER(PshLevelInfo), c_void_p, c_void_p, c_void_p]),
         "inrf_psh_free": (None, [c_void_p]),
+        "inrf_brick_entries": (c_int64, [c_int32]),
+        "inrf_brick_index": (S, [c_int32, c_void_p, c_int64, c_void_p]),
         "inrf_build_bvh": (S, [c_void_p, c_int64, c_void_p, c_int64, POINTER(c_void_p)]),
         "inrf_bvh_get_info": (S, [c_void_p, POINTER(BvhInfo)]),
         "inrf_bvh_copy": (S, [c_void_p, c_void_p, c_void_p]),

@@ -94,7 +94,7 @@ __device__ __forceinline__ void level_scatter(const ModelC& m, const LevelC& L, 
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         const float wc = ((c & 1) ? q.wx : ux) * ((c & 2) ? q.wy : uy) * ((c & 4) ? q.wz : uz);
-        float* p = d_table + 2 * (L.slot_off + level_slot(L, q, c));
+        float* p = d_table + 2 * (L.slot_off + level_store(L, q, c));
         unsafeAtomicAdd(p, wc * de0);
         unsafeAtomicAdd(p + 1, wc * de1);
     }

@@ -7,6 +7,7 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
+#include "brick_layout.hpp"
 #include "bvh_layout.hpp"
 #include "inrf.h"
 
@@ -16,6 +17,8 @@ namespace dev {
 struct LevelC {
     int32_t res, mbar, rbar, pad;
     uint32_t magic_mbar, magic_rbar;  // ceil(2^32 / m): p mod m = p - m * umulhi(p, magic)
+    uint32_t row_m, plane_m, row_r, plane_r;  // brick_row / brick_plane of the two cubes
+    uint32_t last_m, pad2;                    // brick_entries(mbar) - 1
     int64_t phi_off, slot_off;
 };
 
@@ -62,14 +65,21 @@ __device__ __forceinline__ float clamp01(float v) { return fminf(fmaxf(v, 0.f), 
 
 template <class T>
 struct TableRead;
+// Feature pair of entry i of a level's table starting at `base` (the entry
+// offset in bytes fits 32 bits: the host bounds every level's table below
+// 4 GiB), so the load takes a wave-uniform base and a 32-bit lane offset.
 template <>
 struct TableRead<float> {
-    __device__ static float2 get(const void* t, int64_t i) { return reinterpret_cast<const float2*>(t)[i]; }
+    typedef float2 elem;
+    __device__ static float2 get(const char* base, uint32_t i) {
+        return *reinterpret_cast<const float2*>(base + (i << 3));
+    }
 };
 template <>
 struct TableRead<__half> {
-    __device__ static float2 get(const void* t, int64_t i) {
-        return __half22float2(reinterpret_cast<const __half2*>(t)[i]);
+    typedef __half2 elem;
+    __device__ static float2 get(const char* base, uint32_t i) {
+        return __half22float2(*reinterpret_cast<const __half2*>(base + (i << 2)));
     }
 };
 
@@ -102,34 +112,45 @@ __device__ __forceinline__ void level_issue(const ModelC& m, const LevelC& L, fl
     q.hz = mod_small(pz, L.mbar, L.magic_mbar);
     const int qx1 = (qx + 1 == L.rbar) ? 0 : qx + 1, qy1 = (qy + 1 == L.rbar) ? 0 : qy + 1,
               qz1 = (qz + 1 == L.rbar) ? 0 : qz + 1;
-    const uint32_t* phi = m.phi + L.phi_off;
+    const uint32_t X[2] = {brick_x(qx), brick_x(qx1)};
+    const uint32_t Y[2] = {brick_y(qy, L.row_r), brick_y(qy1, L.row_r)};
+    const uint32_t Z[2] = {brick_z(qz, L.plane_r), brick_z(qz1, L.plane_r)};
+    const char* phi = reinterpret_cast<const char*>(m.phi + L.phi_off);
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const int cx = (c & 1) ? qx1 : qx, cy = (c & 2) ? qy1 : qy, cz = (c & 4) ? qz1 : qz;
-        q.o[c] = phi[(cz * L.rbar + cy) * L.rbar + cx];
-    }
+    for (int c = 0; c < 8; ++c)
+        q.o[c] = *reinterpret_cast<const uint32_t*>(phi + ((X[c & 1] + Y[(c >> 1) & 1] + Z[c >> 2]) << 2));
 }
 
-// Linear slot of corner c once its offset has arrived.  (p + c) mod mbar is
-// at most mbar and a valid offset is below mbar, so one wrap reduces each
-// component; the final clamp keeps even a corrupt offset inside the level.
-__device__ __forceinline__ int level_slot(const LevelC& L, const LevelQuery& q, int c) {
-    const int sx = wrap_once(q.hx + ((c & 1) ? 1 : 0) + int(q.o[c] & 1023u), L.mbar);
-    const int sy = wrap_once(q.hy + ((c & 2) ? 1 : 0) + int((q.o[c] >> 10) & 1023u), L.mbar);
-    const int sz = wrap_once(q.hz + ((c & 4) ? 1 : 0) + int((q.o[c] >> 20) & 1023u), L.mbar);
-    const int s = (sz * L.mbar + sy) * L.mbar + sx;
-    return min(s, L.mbar * L.mbar * L.mbar - 1);
+// Slot of corner c once its offset has arrived, as cube coordinates.
+// (p + c) mod mbar is at most mbar and a valid offset is below mbar, so one
+// wrap reduces each component.
+__device__ __forceinline__ void level_slot3(const LevelC& L, const LevelQuery& q, int c, uint32_t& sx, uint32_t& sy,
+                                            uint32_t& sz) {
+    sx = uint32_t(wrap_once(q.hx + ((c & 1) ? 1 : 0) + int(q.o[c] & 1023u), L.mbar));
+    sy = uint32_t(wrap_once(q.hy + ((c & 2) ? 1 : 0) + int((q.o[c] >> 10) & 1023u), L.mbar));
+    sz = uint32_t(wrap_once(q.hz + ((c & 4) ? 1 : 0) + int((q.o[c] >> 20) & 1023u), L.mbar));
+}
+
+// Storage index (in the level's table) of corner c's slot; the clamp keeps
+// even a corrupt offset table inside the level.
+__device__ __forceinline__ uint32_t level_store(const LevelC& L, const LevelQuery& q, int c) {
+    uint32_t sx, sy, sz;
+    level_slot3(L, q, c, sx, sy, sz);
+    return min(brick_x(sx) + brick_y(sy, L.row_m) + brick_z(sz, L.plane_m), L.last_m);
 }
 
 // Feature loads of the eight corners.
 template <class T>
 __device__ __forceinline__ void level_fetch(const ModelC& m, const LevelC& L, const LevelQuery& q, float2* f,
                                             int32_t* __restrict__ slots_out) {
+    const char* base = reinterpret_cast<const char*>(
+        reinterpret_cast<const typename TableRead<T>::elem*>(m.table) + L.slot_off);
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-        const int s = level_slot(L, q, c);
-        f[c] = TableRead<T>::get(m.table, L.slot_off + s);
-        if (slots_out) slots_out[c] = s;
+        uint32_t sx, sy, sz;
+        level_slot3(L, q, c, sx, sy, sz);
+        f[c] = TableRead<T>::get(base, min(brick_x(sx) + brick_y(sy, L.row_m) + brick_z(sz, L.plane_m), L.last_m));
+        if (slots_out) slots_out[c] = int(__umul24(__umul24(sz, L.mbar) + sy, L.mbar) + sx);
     }
 }
 
@@ -145,8 +166,8 @@ __device__ __forceinline__ float2 level_blend(const LevelQuery& q, const float2*
     return e;
 }
 
-// One level, optionally writing the eight level-local linear slots to
-// slots_out[0..7] (global memory).
+// One level, optionally writing the eight level-local linear slots
+// (s_z * mbar + s_y) * mbar + s_x to slots_out[0..7] (global memory).
 template <class T>
 __device__ __forceinline__ float2 encode_level(const ModelC& m, const LevelC& L, float x, float y, float z,
                                                int32_t* __restrict__ slots_out) {

@@ -31,6 +31,7 @@
 #include <string>
 #include <thread>
 
+#include "brick_layout.hpp"
 #include "host_common.hpp"
 #include "host_internal.hpp"
 
@@ -373,5 +374,26 @@ inrf_status inrf_psh_level(const inrf_psh* psh, int32_t level, inrf_psh_level_in
 }
 
 void inrf_psh_free(inrf_psh* psh) { delete psh; }
+
+int64_t inrf_brick_entries(int32_t side) {
+    if (side < 1 || side > 1024) return -1;
+    return inrf::brick_entries(side);
+}
+
+inrf_status inrf_brick_index(int32_t side, const int64_t* linear, int64_t n, int64_t* out) {
+    return guarded("inrf_brick_index", [&] {
+        require(side >= 1 && side <= 1024, "side must be in [1, 1024]");
+        require(n >= 0, "n must be >= 0");
+        require(n == 0 || (linear && out), "NULL buffer");
+        const int64_t s = side, cells = s * s * s;
+        for (int64_t i = 0; i < n; ++i) require(linear[i] >= 0 && linear[i] < cells, "linear index out of range");
+        const uint32_t row = inrf::brick_row(side), plane = inrf::brick_plane(side);
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t v = linear[i];
+            const int x = int(v % s), y = int((v / s) % s), z = int(v / (s * s));
+            out[i] = int64_t(inrf::brick_x(x)) + inrf::brick_y(y, row) + inrf::brick_z(z, plane);
+        }
+    });
+}
 
 }  // extern "C"

@@ -693,6 +693,15 @@ ModelC make_model(const inrf_model* m, bool need_table, bool need_bvh) {
         L.rbar = d.rbar;
         L.magic_mbar = uint32_t(((uint64_t(1) << 32) + uint64_t(d.mbar) - 1) / uint64_t(d.mbar));
         L.magic_rbar = uint32_t(((uint64_t(1) << 32) + uint64_t(d.rbar) - 1) / uint64_t(d.rbar));
+        L.row_m = brick_row(d.mbar);
+        L.plane_m = brick_plane(d.mbar);
+        L.row_r = brick_row(d.rbar);
+        L.plane_r = brick_plane(d.rbar);
+        // table entries of the level are addressed with 32-bit byte offsets
+        const int64_t entries = brick_entries(d.mbar);
+        L.last_m = uint32_t(entries - 1);
+        const int64_t elem = m->table_dtype == INRF_F32 ? 8 : 4;
+        require(entries * elem <= (int64_t(1) << 32), "a level's table must be below 4 GiB (mbar too large for FP32)");
         L.phi_off = d.phi_offset;
         L.slot_off = d.slot_offset;
     }

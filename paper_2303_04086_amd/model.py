@@ -32,6 +32,28 @@ class PshLevel:
         return np.stack([k % M, (k // M) % M, k // (M * M)], axis=1)
 
 
+def brick_entries(side: int) -> int:
+    """Entries one level's cube of the given side occupies on the device."""
+    n = int(L.lib().inrf_brick_entries(int(side)))
+    if n < 0:
+        raise ValueError(f"side {side} not in [1, 1024]")
+    return n
+
+
+def brick_index(side: int, linear) -> np.ndarray:
+    """Device storage index of linear cell indices (z*side + y)*side + x."""
+    lin = np.ascontiguousarray(linear, np.int64)
+    out = np.empty_like(lin)
+    L.check(L.lib().inrf_brick_index(int(side), L.ptr(lin), lin.size, L.ptr(out)))
+    return out
+
+
+def table_index(R, level: int, slots) -> np.ndarray:
+    """Row of the device table holding linear slot(s) `slots` of `level`."""
+    _, mbar, _, _, so = R.level_desc[level]
+    return so + brick_index(mbar, slots)
+
+
 def psh_params(**kw) -> L.PshParams:
     p = L.PshParams()
     L.lib().inrf_psh_params_default(ctypes.byref(p))
@@ -147,14 +169,18 @@ class Renderer:
         self.level_desc = []
         for lv in self.levels:
             self.level_desc.append((lv.res, lv.mbar, lv.rbar, phi_off, slot_off))
-            phi_off += len(lv.phi)
-            slot_off += lv.mbar ** 3
+            phi_off += brick_entries(lv.rbar)
+            slot_off += brick_entries(lv.mbar)
         self.n_slots = slot_off
-        self.phi = torch.from_numpy(np.concatenate([lv.phi for lv in self.levels]).view(np.int32)).to(self.device)
+        phi = np.zeros(phi_off, np.uint32)
         host = np.zeros((slot_off, L.FEATURES), np.float32)
         for l, lv in enumerate(self.levels):
+            po, so = self.level_desc[l][3], self.level_desc[l][4]
+            phi[po + brick_index(lv.rbar, np.arange(len(lv.phi), dtype=np.int64))] = lv.phi
             f = np.asarray(features(l, lv), np.float32)
-            host[self.level_desc[l][4] + lv.slots.astype(np.int64)] = f
+            host[so + brick_index(lv.mbar, lv.slots.astype(np.int64))] = f
+        self.phi = torch.from_numpy(phi.view(np.int32)).to(self.device)
+        del phi
         self.tables = {}
         t32 = torch.from_numpy(host)
         for name in tables:

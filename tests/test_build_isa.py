@@ -8,7 +8,12 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
+_CACHE = {}
+
+
 def _assembly(tmp_path):
+    if "asm" in _CACHE:
+        return _CACHE["asm"]
     from paper_2303_04086_amd import build as b
     out = tmp_path / "render.s"
     cmd = [b._hipcc(), *b.HIP_FLAGS, *b.COMMON, "--cuda-device-only", "-S",
@@ -16,7 +21,8 @@ def _assembly(tmp_path):
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         pytest.skip(f"hipcc unavailable: {r.stderr[:200]}")
-    return out.read_text()
+    _CACHE["asm"] = out.read_text()
+    return _CACHE["asm"]
 
 
 def test_no_partially_overlapping_matrix_accumulators(tmp_path):

@@ -14,6 +14,7 @@ import pytest
 import oracle
 import synth
 from gpu_helpers import compare_hits, make_renderer
+from paper_2303_04086_amd.model import table_index
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -93,7 +94,7 @@ def _check_table(R, dt, ref, opsh, what):
             continue
         verts = np.array(list(ref["features"][l].keys()), np.int64)
         want = np.array(list(ref["features"][l].values()))
-        slots = R.level_desc[l][4] + oracle.psh_slots(lv, verts).astype(np.int64)
+        slots = table_index(R, l, oracle.psh_slots(lv, verts).astype(np.int64))
         touched[slots] = True
         worst = max(worst, np.abs(dt[slots] - want).max())
     print(f"{what} dTable: max |grad| {scale:.3e}, max abs err {worst:.2e} ({worst / scale:.1e} rel), "

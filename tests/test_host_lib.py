@@ -147,3 +147,31 @@ def test_empty_mesh_builds():
     assert (lv.mbar, lv.rbar) == (O.mbar, O.rbar) and np.array_equal(lv.phi, O.phi)
     b = P.build_bvh(v, t)
     assert b.n_nodes == 1 and b.stack == 1
+
+
+def test_brick_layout():
+    """Storage order of the device cubes: a bijection into the padded cube,
+    bricks of 8 x 4 x 1 cells on one 128-byte line, hand-checked entries."""
+    from paper_2303_04086_amd.model import brick_entries, brick_index
+    for side in (1, 2, 3, 5, 8, 13, 64):
+        n = side ** 3
+        idx = brick_index(side, np.arange(n))
+        assert len(np.unique(idx)) == n and idx.min() >= 0 and idx.max() < brick_entries(side)
+        v = np.arange(n)
+        x, y, z = v % side, (v // side) % side, v // (side * side)
+        key = (z * 1000 + y // 4) * 1000 + x // 8
+        for k in np.unique(key)[:50]:
+            assert len(np.unique(idx[key == k] // 32)) == 1   # one brick = one line
+        assert np.array_equal(idx % 32, (y % 4) * 8 + x % 8)
+        bx = -(-side // 8)
+        assert brick_entries(side) == 32 * bx * (-(-side // 4)) * side
+    lin = lambda x, y, z, s: (z * s + y) * s + x
+    got = brick_index(5, [lin(4, 0, 0, 5), lin(0, 4, 0, 5), lin(0, 0, 2, 5), lin(1, 1, 1, 5)])
+    assert list(got) == [4, 32, 128, 73]
+    got = brick_index(20, [lin(8, 0, 0, 20), lin(0, 4, 0, 20), lin(9, 5, 1, 20)])
+    # row = 32 * 3 bricks = 96 entries, plane = 96 * 5 = 480
+    assert list(got) == [32, 96, 480 + 96 + 32 + 1 * 8 + 1]
+    import paper_2303_04086_amd as P
+    assert P.lib().inrf_brick_entries(0) == -1 and P.lib().inrf_brick_entries(1025) == -1
+    with pytest.raises(P.InrfError):
+        brick_index(5, [0, 125])
