@@ -212,7 +212,7 @@ typedef struct inrf_model {
     const void* bvh_tris;   /* device image from inrf_bvh_copy */
     int64_t n_tris;         /* proxy triangles; 0 = empty proxy (every ray misses) */
     int32_t bvh_stack;      /* inrf_bvh_info.stack of the image (sizes the traversal stack) */
-    int32_t pad1;
+    int32_t bvh_n_nodes;    /* inrf_bvh_info.n_nodes of the image */
 } inrf_model;
 
 /* Pinhole camera (pose and intrinsics as a client sends them).  Pixel (i

@@ -54,7 +54,7 @@ class LevelDesc(ctypes.Structure):
 class ModelDesc(ctypes.Structure):
     _fields_ = [("n_levels", c_int32), ("table_dtype", c_int32), ("levels", LevelDesc * MAX_LEVELS),
                 ("phi", c_void_p), ("table", c_void_p), ("weights", c_void_p), ("bvh_nodes", c_void_p),
-                ("bvh_tris", c_void_p), ("n_tris", c_int64), ("bvh_stack", c_int32), ("pad1", c_int32)]
+                ("bvh_tris", c_void_p), ("n_tris", c_int64), ("bvh_stack", c_int32), ("bvh_n_nodes", c_int32)]
 
 
 class CameraDesc(ctypes.Structure):

@@ -236,6 +236,29 @@ struct Collapser {
     }
 };
 
+// Renumbers the nodes in breadth-first order (the root stays 0): the top
+// levels of the hierarchy, which every ray visits, share cache lines and
+// pages at the start of the image.
+std::vector<BvhNode> breadth_first(const std::vector<BvhNode>& in) {
+    std::vector<int32_t> order, renum(in.size(), -1);
+    order.reserve(in.size());
+    if (!in.empty()) order.push_back(0);
+    for (size_t h = 0; h < order.size(); ++h) {
+        renum[size_t(order[h])] = int32_t(h);
+        for (int c = 0; c < 4; ++c) {
+            const int32_t r = in[size_t(order[h])].child[c];
+            if (r >= 0) order.push_back(r);
+        }
+    }
+    std::vector<BvhNode> out(order.size());
+    for (size_t h = 0; h < order.size(); ++h) {
+        out[h] = in[size_t(order[h])];
+        for (int c = 0; c < 4; ++c)
+            if (out[h].child[c] >= 0) out[h].child[c] = renum[size_t(out[h].child[c])];
+    }
+    return out;
+}
+
 }  // namespace
 }  // namespace inrf
 
@@ -283,7 +306,7 @@ inrf_status inrf_build_bvh(const float* verts, int64_t n_verts, const int32_t* t
         const int32_t stack = C.collapse(0, 1, &root);
         if (stack > kBvhMaxStack) fail(INRF_E_BUILD, "traversal would need more than 64 stack entries");
         auto* obj = new inrf_bvh();
-        obj->nodes = std::move(C.out);
+        obj->nodes = breadth_first(C.out);
         obj->depth = C.depth + 1;  // leaves sit below the deepest node
         obj->stack = std::max(1, stack);
         obj->tris.resize(size_t(n_tris));

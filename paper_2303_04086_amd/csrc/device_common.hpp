@@ -31,7 +31,7 @@ struct ModelC {
     const BvhTri* tris;
     int64_t n_tris;
     int32_t stack_depth;  // traversal stack entries per lane (the image's bound, >= 1)
-    int32_t pad;
+    int32_t n_nodes;      // nodes of the image
     LevelC lv[INRF_MAX_LEVELS];
 };
 

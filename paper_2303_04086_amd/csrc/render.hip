@@ -378,38 +378,75 @@ __global__ __launch_bounds__(kThreads) void k_trace(ModelC m, CamC cam, TraceArg
     }
 }
 
-// Exclusive prefix sum of the workgroups' hit counts (one workgroup of
-// 1024 threads, each summing a contiguous run), and the total into *counter.
-constexpr int kScanThreads = 1024;
-__global__ __launch_bounds__(kScanThreads) void k_scan(const int2* __restrict__ blk, int n_blk,
-                                                       int32_t* __restrict__ offsets, int32_t* __restrict__ counter) {
-    __shared__ int s[kScanThreads];
-    const int per = (n_blk + kScanThreads - 1) / kScanThreads;
-    const int lo = min(n_blk, int(threadIdx.x) * per), hi = min(n_blk, lo + per);
-    int sum = 0;
-    for (int i = lo; i < hi; ++i) sum += blk[i].x;
-    s[threadIdx.x] = sum;
+// Exclusive prefix sum of the per-tile hit counts in two levels: k_scan_local
+// scans runs of kScanRun counts (one workgroup each) and writes each run's
+// total; k_scan_runs scans those totals (one workgroup) and writes the grand
+// total to the counter.  k_compact adds the two.
+constexpr int kScanThreads = 1024, kScanRun = 2 * kScanThreads;
+
+// Inclusive sum of v over the lanes of a wave up to this one.
+__device__ __forceinline__ int wave_scan(int v) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int u = __shfl_up(v, d);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
+// Exclusive block-wide prefix of v (kScanThreads threads); *total gets the sum.
+__device__ __forceinline__ int block_exclusive(int v, int* s_wave, int* total) {
+    const int lane = __lane_id(), wave = threadIdx.x / 64;
+    const int inc = wave_scan(v);
+    if (lane == 63) s_wave[wave] = inc;
     __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {  // inclusive Hillis-Steele scan
-        const int v = threadIdx.x >= unsigned(off) ? s[threadIdx.x - off] : 0;
-        __syncthreads();
-        s[threadIdx.x] += v;
+    if (wave == 0) {
+        const int w = lane < kScanThreads / 64 ? s_wave[lane] : 0;
+        const int wi = wave_scan(w);
+        if (lane < kScanThreads / 64) s_wave[lane] = wi - w;  // exclusive over waves
+        if (lane == kScanThreads / 64 - 1) s_wave[kScanThreads / 64] = wi;
+    }
+    __syncthreads();
+    *total = s_wave[kScanThreads / 64];
+    return s_wave[wave] + inc - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_local(const int2* __restrict__ blk, int n_blk,
+                                                             int32_t* __restrict__ offsets, int32_t* __restrict__ runs) {
+    __shared__ int s_wave[kScanThreads / 64 + 1];
+    const int i0 = blockIdx.x * kScanRun + 2 * threadIdx.x;
+    const int c0 = i0 < n_blk ? blk[i0].x : 0, c1 = i0 + 1 < n_blk ? blk[i0 + 1].x : 0;
+    int total;
+    const int ex = block_exclusive(c0 + c1, s_wave, &total);
+    if (i0 < n_blk) offsets[i0] = ex;
+    if (i0 + 1 < n_blk) offsets[i0 + 1] = ex + c0;
+    if (threadIdx.x == 0) runs[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_runs(int32_t* __restrict__ runs, int n_runs,
+                                                            int32_t* __restrict__ counter) {
+    __shared__ int s_wave[kScanThreads / 64 + 1];
+    int carry = 0;
+    for (int r0 = 0; r0 < n_runs; r0 += kScanThreads) {  // n_runs is small: usually one pass
+        const int i = r0 + threadIdx.x;
+        const int v = i < n_runs ? runs[i] : 0;
+        int total;
+        const int ex = block_exclusive(v, s_wave, &total);
+        if (i < n_runs) runs[i] = carry + ex;
+        carry += total;
         __syncthreads();
     }
-    int run = s[threadIdx.x] - sum;
-    for (int i = lo; i < hi; ++i) {
-        offsets[i] = run;
-        run += blk[i].x;
-    }
-    if (threadIdx.x == kScanThreads - 1) *counter = s[kScanThreads - 1];
+    if (threadIdx.x == 0) *counter = carry;
 }
 
 // Packs the workgroups' records into one list in workgroup order (tile
 // raster order for a camera), so the list does not depend on timing.
 __global__ __launch_bounds__(kThreads) void k_compact(const int2* __restrict__ blk, const int32_t* __restrict__ offsets,
-                                                      const HitRec* __restrict__ tmp, HitRec* __restrict__ recs) {
+                                                      const int32_t* __restrict__ runs, const HitRec* __restrict__ tmp,
+                                                      HitRec* __restrict__ recs) {
     const int2 b = blk[blockIdx.x];
-    const int32_t off = offsets[blockIdx.x];
+    const int32_t off = offsets[blockIdx.x] + runs[blockIdx.x / kScanRun];
     for (int i = threadIdx.x; i < b.x; i += kThreads) {
         const float4* src = reinterpret_cast<const float4*>(tmp + b.y + i);
         float4* dst = reinterpret_cast<float4*>(recs + off + i);
@@ -621,18 +658,20 @@ constexpr int64_t kWsHeader = 256;
 
 int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
 
-// Workspace of a trace of up to n rays: counter | records | per-workgroup
-// records | per-workgroup (count, base) | per-workgroup offsets.  A camera
-// of W x H = n pixels has at most ceil(W/16) ceil(H/16) <= n/8 + 2 tiles.
+// Workspace of a trace of up to n rays: counter | records | per-tile
+// records | per-tile (count, base) | per-tile offsets | per-run offsets.  A
+// camera of W x H = n pixels has at most ceil(W/16) ceil(H/16) <= n/8 + 2
+// tiles.
 struct WsLayout {
-    int64_t recs, tmp, blk, offsets, end;
+    int64_t recs, tmp, blk, offsets, runs, end;
     explicit WsLayout(int64_t n) {
-        const int64_t nb = n / 8 + 2;
+        const int64_t nb = n / 8 + 2, nr = nb / kScanRun + 1;
         recs = kWsHeader;
         tmp = align256(recs + n * int64_t(sizeof(HitRec)));
         blk = align256(tmp + n * int64_t(sizeof(HitRec)));
         offsets = align256(blk + nb * int64_t(sizeof(int2)));
-        end = align256(offsets + nb * int64_t(sizeof(int32_t)));
+        runs = align256(offsets + nb * int64_t(sizeof(int32_t)));
+        end = align256(runs + nr * int64_t(sizeof(int32_t)));
     }
 };
 
@@ -678,7 +717,9 @@ ModelC make_model(const inrf_model* m, bool need_table, bool need_bvh) {
         require(m->n_tris == 0 || (m->bvh_nodes && m->bvh_tris), "bvh images must be set");
         require(m->n_tris == 0 || (m->bvh_stack >= 1 && m->bvh_stack <= kBvhMaxStack),
                 "bvh_stack must be the image's stack bound (1..64)");
+        require(m->n_tris == 0 || m->bvh_n_nodes >= 1, "bvh_n_nodes must be the image's node count");
         c.stack_depth = std::max(1, m->bvh_stack);
+        c.n_nodes = m->n_tris == 0 ? 0 : m->bvh_n_nodes;
     }
     for (int l = 0; l < m->n_levels; ++l) {
         const inrf_level_desc& d = m->levels[l];
@@ -785,6 +826,24 @@ void record(void* const* events, int i, hipStream_t s) {
 
 // Clears the hit counter, then traces n rays (camera rays when cam is set),
 // writing depth / triangle / zero colour of misses and appending hit records.
+// Launches k_trace, one workgroup per tile (camera) or 256-ray block
+// (batch); returns the number of workgroups.
+int launch_trace(const ModelC& c, const CamC* cam, const TraceArgs& a, int64_t n, hipStream_t s) {
+    if (cam) {
+        const int n_blk = cam->tiles_x * ((cam->H + kTile - 1) / kTile);
+        hipLaunchKernelGGL(k_trace<true>, dim3(n_blk), dim3(kThreads), 0, s, c, *cam, a);
+        launch_check("k_trace");
+        return n_blk;
+    }
+    CamC none;
+    std::memset(&none, 0, sizeof(none));
+    const int n_blk = int((n + kThreads - 1) / kThreads);
+    const size_t stack_bytes = size_t(c.stack_depth) * kThreads * sizeof(int);
+    hipLaunchKernelGGL(k_trace<false>, dim3(n_blk), dim3(kThreads), stack_bytes, s, c, none, a);
+    launch_check("k_trace");
+    return n_blk;
+}
+
 // Traces n rays (camera rays when cam is set), writing depth / triangle /
 // zero colour of misses, then packs the hit records into one list in
 // workgroup order and writes its length to the counter.
@@ -795,22 +854,15 @@ void trace_to_hits(const ModelC& c, const CamC* cam, const float* ray_o, const f
     HitRec* recs = ws_at<HitRec>(ws, L.recs);
     int2* blk = ws_at<int2>(ws, L.blk);
     int32_t* offsets = ws_at<int32_t>(ws, L.offsets);
+    int32_t* runs = ws_at<int32_t>(ws, L.runs);
     TraceArgs a{ray_o, ray_d, n, rgba, depth, tri, ws_at<HitRec>(ws, L.tmp), blk};
-    int n_blk;
-    if (cam) {
-        n_blk = cam->tiles_x * ((cam->H + kTile - 1) / kTile);
-        hipLaunchKernelGGL(k_trace<true>, dim3(n_blk), dim3(kThreads), 0, s, c, *cam, a);
-    } else {
-        CamC none;
-        std::memset(&none, 0, sizeof(none));
-        n_blk = int((n + kThreads - 1) / kThreads);
-        const size_t stack_bytes = size_t(c.stack_depth) * kThreads * sizeof(int);
-        hipLaunchKernelGGL(k_trace<false>, dim3(n_blk), dim3(kThreads), stack_bytes, s, c, none, a);
-    }
-    launch_check("k_trace");
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, blk, n_blk, offsets, counter);
-    launch_check("k_scan");
-    hipLaunchKernelGGL(k_compact, dim3(n_blk), dim3(kThreads), 0, s, blk, offsets, a.tmp, recs);
+    const int n_blk = launch_trace(c, cam, a, n, s);
+    const int n_runs = (n_blk + kScanRun - 1) / kScanRun;
+    hipLaunchKernelGGL(k_scan_local, dim3(n_runs), dim3(kScanThreads), 0, s, blk, n_blk, offsets, runs);
+    launch_check("k_scan_local");
+    hipLaunchKernelGGL(k_scan_runs, dim3(1), dim3(kScanThreads), 0, s, runs, n_runs, counter);
+    launch_check("k_scan_runs");
+    hipLaunchKernelGGL(k_compact, dim3(n_blk), dim3(kThreads), 0, s, blk, offsets, runs, a.tmp, recs);
     launch_check("k_compact");
 }
 
@@ -994,13 +1046,8 @@ inrf_status inrf_trace(const inrf_model* m, const float* ray_o, const float* ray
         require(n >= 0 && n <= (int64_t(1) << 31) - 1, "n must be in [0, 2^31)");
         require(n == 0 || (ray_o && ray_d && tri && t), "NULL buffer");
         if (n == 0) return;
-        dev::TraceArgs a{ray_o, ray_d, n, nullptr, t, tri, nullptr, nullptr};  // no records
-        dev::CamC none;
-        std::memset(&none, 0, sizeof(none));
-        const size_t stack_bytes = size_t(c.stack_depth) * dev::kThreads * sizeof(int);
-        hipLaunchKernelGGL(dev::k_trace<false>, dim3(unsigned((n + dev::kThreads - 1) / dev::kThreads)),
-                           dim3(dev::kThreads), stack_bytes, reinterpret_cast<hipStream_t>(stream), c, none, a);
-        launch_check("k_trace");
+        const dev::TraceArgs a{ray_o, ray_d, n, nullptr, t, tri, nullptr, nullptr};  // no records
+        launch_trace(c, nullptr, a, n, reinterpret_cast<hipStream_t>(stream));
     });
 }
 

@@ -216,6 +216,7 @@ class Renderer:
             m.bvh_tris = self.bvh_tris.data_ptr()
             m.n_tris = self.n_tris
             m.bvh_stack = self.bvh.stack
+            m.bvh_n_nodes = self.bvh.n_nodes
             self._descs[table] = m
         return self._descs[table]
 
