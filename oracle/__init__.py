@@ -30,10 +30,11 @@ from .mlp import mlp_forward
 from .render import Model, render_rays, render_camera, encode_points
 from .backward import backward_rays, mse_loss, mse_grad
 from .optim import adam_step
+from .scene import Instance, render_scene_rays
 
 __all__ = [
     "camera_rays", "closest_hit", "HitResult", "surface_cells", "shell_keys",
     "build_psh_level", "psh_slots", "PSHLevel", "grid_cell", "trilinear_encode",
     "FeatureGrid", "sh_real", "mlp_forward", "Model", "render_rays",
-    "render_camera", "encode_points", "backward_rays", "mse_loss", "mse_grad", "adam_step",
+    "render_camera", "encode_points", "backward_rays", "mse_loss", "mse_grad", "adam_step", "Instance", "render_scene_rays",
 ]
