@@ -217,6 +217,50 @@ def train_bench(torch, R, w, steps, batch):
             "note": "forward + backward + dense Adam over the whole FP32 table each step; stand-in targets"}
 
 
+def scene_bench(torch, P, frames, W, H):
+    """Multi-object scene: 12 objects with their own tables and networks,
+    merged per pixel by depth; FP16 and FP32 paths at W x H."""
+    import synth
+    sc = synth.scene_objects(12, W, H)
+    t0 = time.time()
+    rs = []
+    keys = 0
+    for o in sc.objects:
+        w = o.workload
+        R = P.Renderer(w.verts, w.tris, w.res, w.weights,
+                       lambda l, lv, w=w: synth.feature_values(w.feature_seed, l, lv.keys, F=w.F),
+                       tables=("f32", "f16"), dilate=w.dilate, seed=w.psh_seed)
+        keys += sum(len(lv.keys) for lv in R.levels)
+        rs.append(R)
+    S = P.Scene(rs, [(o.scale, o.rotation, o.translation) for o in sc.objects])
+    log(f"scene of {len(rs)} objects resident ({keys} keys) in {time.time() - t0:.1f} s")
+    out = {"workload": sc.name, "objects": len(rs), "keys": keys,
+           "triangles": int(sum(len(o.workload.tris) for o in sc.objects))}
+    rgba = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
+    obj = torch.empty(H * W, dtype=torch.int32, device="cuda")
+    for prec, table in (("fp16", "f16"), ("fp32", "f32")):
+        for i in range(3):
+            S.render(sc.cameras[i % len(sc.cameras)], prec, table, rgba=rgba)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(frames + 1)]
+        ev[0].record()
+        for i in range(frames):
+            S.render(sc.cameras[i % len(sc.cameras)], prec, table, rgba=rgba)
+            ev[i + 1].record()
+        torch.cuda.synchronize()
+        ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(frames)]
+        S.render(sc.cameras[0], prec, table, rgba=rgba, obj=obj)
+        torch.cuda.synchronize()
+        hit = float((obj >= 0).float().mean())
+        out[prec] = {"Mrays_per_s": round(W * H * frames / (sum(ms) / 1e3) / 1e6, 1),
+                     "ms_per_frame": round(sum(ms) / frames, 4), "p99_ms": round(pct(ms, 99), 4),
+                     "hit_fraction_camera0": round(hit, 4)}
+        log(f"scene {prec}: {out[prec]}")
+    del S, rs
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,6 +277,7 @@ def main():
     ap.add_argument("--sweep-frames", type=int, default=8, help="frames per sweep case (0: no sweep)")
     ap.add_argument("--train-steps", type=int, default=10, help="timed training steps (0: none)")
     ap.add_argument("--train-batch", type=int, default=1 << 18)
+    ap.add_argument("--scene-frames", type=int, default=16, help="timed frames of the 12-object scene (0: none)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times), the reference "
                          "for scaling hardware byte counters, and exit")
@@ -288,6 +333,7 @@ def main():
             mlp[prec] = mlp_bench(torch, R, prec, args.mlp_rays)
             log(f"mlp {prec}: {mlp[prec]}")
     sweep = sweep_bench(torch, R, w, args.sweep_frames) if args.sweep_frames > 0 else None
+    scene = scene_bench(torch, P, args.scene_frames, W, H) if args.scene_frames > 0 else None
     train = None
     if args.train_steps > 0:
         train = train_bench(torch, R, w, args.train_steps, args.train_batch)
@@ -333,6 +379,7 @@ def main():
                      "avg_launch_ms": round(shade_avg_s * 1e3, 4)},
         "mlp": mlp or None,
         "sweep": sweep,
+        "scene": scene,
         "train": train,
         "cpu_baseline": base,
         "source": source_hash(),

@@ -60,6 +60,7 @@ typedef int32_t inrf_status;
 #define INRF_SH_DIM 16   /* real SH bands 0..3 */
 #define INRF_HIDDEN 64   /* width of both hidden layers */
 #define INRF_OUT 4       /* R, G, B, alpha */
+#define INRF_MAX_OBJECTS 16 /* objects of one scene render */
 
 /* Thread-local message of the last failed call ("" if none). */
 const char* inrf_last_error(void);
@@ -270,6 +271,40 @@ inrf_status inrf_mlp(const inrf_model* m, int32_t precision, const float* in, in
                      void* stream);
 
 /* ------------------------------------------------------------------------
+ * Scenes of several objects (the paper composes objects per pixel by depth,
+ * Sec. 5; scenes of several objects, Sec. 7).
+ * ---------------------------------------------------------------------- */
+
+/* One object of a scene: its model (host pointer to the model view, whose
+ * device memory must stay valid until the render completes) placed in the
+ * world by a similarity transform
+ *     x_world = scale * rotation * x_object + translation,
+ * scale > 0, rotation row-major, orthonormal with determinant +1. */
+typedef struct inrf_instance {
+    const inrf_model* model;
+    float scale;
+    float rotation[9];
+    float translation[3];
+} inrf_instance;
+
+/* Workspace bytes inrf_render_scene needs for n_objects and n_rays pixels;
+ * -1 on invalid arguments. */
+int64_t inrf_scene_workspace_size(int32_t n_objects, int64_t n_rays);
+
+/* Render one camera over a scene of n_objects (0..INRF_MAX_OBJECTS) objects:
+ * per pixel the nearest hit over all objects wins (equal distance: the lower
+ * object index), and that object's network shades it from the object-space
+ * hit point and direction.  rgba as inrf_render; depth (nullable) is the
+ * world distance along the unit ray; tri (nullable) the triangle of the
+ * winning object's proxy; object (nullable, device int32 [height*width]) the
+ * winning object's index, -1 on a miss.  Every object's model uses the same
+ * precision; tables may differ in type.  ws: 256-byte aligned, at least
+ * inrf_scene_workspace_size(n_objects, width*height) bytes. */
+inrf_status inrf_render_scene(const inrf_instance* objects, int32_t n_objects, int32_t precision,
+                              const inrf_camera* cam, float* rgba, float* depth, int32_t* tri, int32_t* object,
+                              void* ws, int64_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Gradient (training, Sec. 4.2 with the loss of Eq. 8).
  * ---------------------------------------------------------------------- */
 
@@ -292,7 +327,8 @@ int64_t inrf_backward_workspace_size(const inrf_model* m, int64_t n_rays);
  *   rgba      optional device float32 [n][4]: the forward output the
  *             gradient was taken at (FP32 network), written if set.
  * The network runs in FP32 (matrix cores) whatever precision inrf_forward
- * used; a missed ray contributes nothing.  Activations are recomputed, not
+ * used; a missed ray contributes nothing.  Models of up to 16 levels
+ * (INRF_E_UNSUPPORTED beyond).  Activations are recomputed, not
  * read from a previous forward call.  ws: device workspace, 256-byte
  * aligned, of at least inrf_backward_workspace_size(m, n) bytes. */
 inrf_status inrf_backward(const inrf_model* m, const float* ray_o, const float* ray_d, int64_t n,

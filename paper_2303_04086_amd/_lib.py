@@ -14,6 +14,7 @@ INRF_OK, INRF_E_INVALID, INRF_E_SIZE, INRF_E_BUILD, INRF_E_DEVICE, INRF_E_UNSUPP
 INRF_F32, INRF_F16, INRF_BF16 = 0, 1, 2
 PREC_FP32, PREC_FP16, PREC_BF16 = 0, 1, 2
 MAX_LEVELS, FEATURES, SH_DIM, HIDDEN, OUT = 32, 2, 16, 64, 4
+MAX_OBJECTS = 16
 
 EXPORTED = [
     "inrf_last_error", "inrf_version", "inrf_psh_params_default", "inrf_build_psh", "inrf_build_psh_keys",
@@ -21,7 +22,8 @@ EXPORTED = [
     "inrf_build_bvh", "inrf_bvh_get_info",
     "inrf_bvh_copy", "inrf_bvh_free", "inrf_workspace_size", "inrf_render", "inrf_render_profiled",
     "inrf_forward", "inrf_trace",
-    "inrf_encode", "inrf_mlp", "inrf_backward_workspace_size", "inrf_backward", "inrf_adam",
+    "inrf_encode", "inrf_mlp", "inrf_scene_workspace_size", "inrf_render_scene", "inrf_backward_workspace_size",
+    "inrf_backward", "inrf_adam",
 ]
 
 
@@ -63,6 +65,11 @@ class CameraDesc(ctypes.Structure):
                 ("height", c_int32)]
 
 
+class InstanceDesc(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_void_p), ("scale", ctypes.c_float), ("rotation", ctypes.c_float * 9),
+                ("translation", ctypes.c_float * 3)]
+
+
 class AdamParams(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
                 ("eps", ctypes.c_float), ("step", c_int64), ("zero_grad", c_int32), ("pad", c_int32)]
@@ -99,6 +106,9 @@ def _declare(lib):
         "inrf_trace": (S, [POINTER(ModelDesc), c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
         "inrf_encode": (S, [POINTER(ModelDesc), c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
         "inrf_mlp": (S, [POINTER(ModelDesc), c_int32, c_void_p, c_int64, c_void_p, c_void_p]),
+        "inrf_scene_workspace_size": (c_int64, [c_int32, c_int64]),
+        "inrf_render_scene": (S, [POINTER(InstanceDesc), c_int32, c_int32, POINTER(CameraDesc), c_void_p, c_void_p,
+                                  c_void_p, c_void_p, c_void_p, c_int64, c_void_p]),
         "inrf_backward_workspace_size": (c_int64, [POINTER(ModelDesc), c_int64]),
         "inrf_backward": (S, [POINTER(ModelDesc), c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p,
                               c_void_p, c_void_p, c_int64, c_void_p]),

@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "bvh_layout.hpp"
 #include "device_common.hpp"
@@ -233,10 +234,12 @@ __device__ void closest_hit(const ModelC& m, const RayPre& R, int* stack, float&
 // deferred nodes is wave-uniform (`wst`, m.stack_depth entries in LDS).
 // Children are ordered by the entry distance of the lowest lane that hits
 // them.
-__device__ void closest_hit_packet(const ModelC& m, const RayPre& R, bool active, int* wst, float& best_t,
+// B is any view with the members nodes, tris, n_tris and stack_depth (a
+// model, or one object of a scene).  best_t / best_i come in as the lane's
+// current closest hit (INFINITY / -1 for none) and are only improved.
+template <class B>
+__device__ void closest_hit_packet(const B& m, const RayPre& R, bool active, int* wst, float& best_t,
                                    int32_t& best_i) {
-    best_t = INFINITY;
-    best_i = -1;
     if (m.n_tris == 0 || __ballot(active) == 0) return;
     int node = 0, sp = 0;
     for (int visits = 0; visits < (1 << 20); ++visits) {
@@ -506,6 +509,7 @@ struct ShadeShape {
 // LDS tile into the matrix-core B-operand layout.
 template <class TableT, class P, int LPG>
 __global__ __launch_bounds__(kThreads) void k_shade(ModelC m, const HitRec* __restrict__ recs,
+                                                    const int32_t* __restrict__ first,
                                                     const int32_t* __restrict__ counter, float* __restrict__ rgba) {
     typedef Mfma<P> M;
     typedef typename M::vec Vec;
@@ -517,9 +521,9 @@ __global__ __launch_bounds__(kThreads) void k_shade(ModelC m, const HitRec* __re
     T* tile = reinterpret_cast<T*>(reinterpret_cast<char*>(lds_v) + weight_bytes(S::F, S::V) +
                                    (threadIdx.x / 64) * S::tile_bytes);
     __syncthreads();
-    const int n = *counter;
+    const int lo = first ? *first : 0, n = *counter;  // records [lo, n)
     const int lane = __lane_id(), g = lane >> 4, r = lane & 15;
-    for (int64_t base = (int64_t(blockIdx.x) * (kThreads / 64) + threadIdx.x / 64) * 64; base < n;
+    for (int64_t base = lo + (int64_t(blockIdx.x) * (kThreads / 64) + threadIdx.x / 64) * 64; base < n;
          base += int64_t(gridDim.x) * kThreads) {
         const int64_t i = base + lane;
         const bool act = i < n;
@@ -646,6 +650,7 @@ __global__ __launch_bounds__(kThreads) void k_mlp(ModelC m, const float* __restr
 }  // namespace inrf
 
 #include "backward_device.hpp"
+#include "scene_device.hpp"
 
 namespace inrf {
 
@@ -770,11 +775,12 @@ unsigned resident_grid(K kernel, size_t lds) {
 }
 
 template <class TableT, class P, int LPG>
-void launch_shade_t(const ModelC& c, const HitRec* recs, const int32_t* counter, float* rgba, hipStream_t s) {
+void launch_shade_t(const ModelC& c, const HitRec* recs, const int32_t* first, const int32_t* counter, float* rgba,
+                    hipStream_t s) {
     const size_t lds = ShadeShape<P, LPG>::lds_bytes;
     auto kern = k_shade<TableT, P, LPG>;
     allow_lds(kern, lds);
-    hipLaunchKernelGGL(kern, dim3(resident_grid(kern, lds)), dim3(kThreads), lds, s, c, recs, counter, rgba);
+    hipLaunchKernelGGL(kern, dim3(resident_grid(kern, lds)), dim3(kThreads), lds, s, c, recs, first, counter, rgba);
 }
 
 template <class P, int LPG>
@@ -790,6 +796,17 @@ void launch_mlp_t(const ModelC& c, const float* in, int64_t n, float* rgba, hipS
 }
 
 // Levels per lane group (ceil(L / 4)) selects the instantiation.
+// The gradient kernel keeps the whole weight gradient in registers, which
+// fits for up to 16 levels.
+#define INRF_LPG_SWITCH_BACKWARD(L, CALL)                             \
+    switch ((L + 3) / 4) {                                            \
+        case 1: CALL(1); break;                                       \
+        case 2: CALL(2); break;                                       \
+        case 3: CALL(3); break;                                       \
+        case 4: CALL(4); break;                                       \
+        default: fail(INRF_E_UNSUPPORTED, "the gradient supports at most 16 levels"); \
+    }
+
 #define INRF_LPG_SWITCH(L, CALL)                              \
     switch ((L + 3) / 4) {                                    \
         case 1: CALL(1); break;                               \
@@ -804,13 +821,14 @@ void launch_mlp_t(const ModelC& c, const float* in, int64_t n, float* rgba, hipS
     }
 
 template <class TableT>
-void launch_shade(const ModelC& c, int32_t precision, const HitRec* recs, const int32_t* counter, float* rgba,
-                  hipStream_t s) {
-#define INRF_SHADE(LPG)                                                                   \
-    do {                                                                                 \
-        if (precision == INRF_PREC_FP32) launch_shade_t<TableT, float, LPG>(c, recs, counter, rgba, s);      \
-        else if (precision == INRF_PREC_FP16) launch_shade_t<TableT, _Float16, LPG>(c, recs, counter, rgba, s); \
-        else launch_shade_t<TableT, __bf16, LPG>(c, recs, counter, rgba, s);             \
+void launch_shade(const ModelC& c, int32_t precision, const HitRec* recs, const int32_t* first,
+                  const int32_t* counter, float* rgba, hipStream_t s) {
+#define INRF_SHADE(LPG)                                                                                 \
+    do {                                                                                               \
+        if (precision == INRF_PREC_FP32) launch_shade_t<TableT, float, LPG>(c, recs, first, counter, rgba, s); \
+        else if (precision == INRF_PREC_FP16)                                                          \
+            launch_shade_t<TableT, _Float16, LPG>(c, recs, first, counter, rgba, s);                   \
+        else launch_shade_t<TableT, __bf16, LPG>(c, recs, first, counter, rgba, s);                    \
     } while (0)
     INRF_LPG_SWITCH(c.n_levels, INRF_SHADE)
 #undef INRF_SHADE
@@ -886,8 +904,8 @@ void run_path(const inrf_model* m, int32_t precision, const CamC* cam, const flo
     record(events, 0, s);
     trace_to_hits(c, cam, ray_o, ray_d, n, rgba, depth, tri, ws, s);
     record(events, 1, s);
-    if (c.table_dtype == INRF_F32) launch_shade<float>(c, precision, recs, counter, rgba, s);
-    else launch_shade<__half>(c, precision, recs, counter, rgba, s);
+    if (c.table_dtype == INRF_F32) launch_shade<float>(c, precision, recs, nullptr, counter, rgba, s);
+    else launch_shade<__half>(c, precision, recs, nullptr, counter, rgba, s);
     launch_check("k_shade");
     record(events, 2, s);
 }
@@ -908,7 +926,7 @@ unsigned backward_grid(const ModelC& c) {
     unsigned g = 0;
 #define INRF_BGRID(LPG) \
     g = c.table_dtype == INRF_F32 ? backward_grid_t<float, LPG>() : backward_grid_t<__half, LPG>()
-    INRF_LPG_SWITCH(c.n_levels, INRF_BGRID)
+    INRF_LPG_SWITCH_BACKWARD(c.n_levels, INRF_BGRID)
 #undef INRF_BGRID
     return g;
 }
@@ -953,7 +971,7 @@ void run_backward(const inrf_model* m, const float* ray_o, const float* ray_d, i
             launch_backward_t<float, LPG>(c, grid, recs, counter, d_rgba, d_table, partial, rgba, s);  \
         else launch_backward_t<__half, LPG>(c, grid, recs, counter, d_rgba, d_table, partial, rgba, s); \
     } while (0)
-    INRF_LPG_SWITCH(c.n_levels, INRF_BACK)
+    INRF_LPG_SWITCH_BACKWARD(c.n_levels, INRF_BACK)
 #undef INRF_BACK
     launch_check("k_backward");
     if (d_weights) {
@@ -982,6 +1000,125 @@ CamC make_camera(const inrf_camera* cam) {
     c.H = cam->height;
     c.tiles_x = (cam->width + kTile - 1) / kTile;
     return c;
+}
+
+// ---- scenes (k_trace_scene)
+
+// Workspace of a scene render of up to n rays and K objects: counter |
+// records | per-tile records | [K][tiles] (count, first) | offsets | runs |
+// K + 1 run starts.
+struct SceneWs {
+    int64_t recs, tmp, blk, offsets, runs, seg, end;
+    SceneWs(int64_t n, int k) {
+        const int64_t nb = int64_t(std::max(k, 1)) * (n / 8 + 2), nr = nb / kScanRun + 1;
+        recs = kWsHeader;
+        tmp = align256(recs + n * int64_t(sizeof(HitRec)));
+        blk = align256(tmp + n * int64_t(sizeof(HitRec)));
+        offsets = align256(blk + nb * int64_t(sizeof(int2)));
+        runs = align256(offsets + nb * int64_t(sizeof(int32_t)));
+        seg = align256(runs + nr * int64_t(sizeof(int32_t)));
+        end = align256(seg + (k + 1) * int64_t(sizeof(int32_t)));
+    }
+};
+
+void make_object(const inrf_instance& in, ObjC& o) {
+    require(in.model != nullptr, "instance model is NULL");
+    const float s = in.scale;
+    require(std::isfinite(s) && s > 0.f, "instance scale must be finite and > 0");
+    const float* R = in.rotation;
+    for (int i = 0; i < 9; ++i) require(std::isfinite(R[i]), "non-finite rotation");
+    for (int i = 0; i < 3; ++i) require(std::isfinite(in.translation[i]), "non-finite translation");
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double dot = 0;
+            for (int k = 0; k < 3; ++k) dot += double(R[3 * i + k]) * R[3 * j + k];
+            require(std::fabs(dot - (i == j ? 1.0 : 0.0)) < 1e-4, "rotation must be orthonormal");
+        }
+    const double det = double(R[0]) * (double(R[4]) * R[8] - double(R[5]) * R[7]) -
+                       double(R[1]) * (double(R[3]) * R[8] - double(R[5]) * R[6]) +
+                       double(R[2]) * (double(R[3]) * R[7] - double(R[4]) * R[6]);
+    require(det > 0.0, "rotation must have determinant +1");
+    // world -> object: x_o = R^T (x_w - t) / s
+    for (int i = 0; i < 3; ++i) {
+        double c = 0;
+        for (int j = 0; j < 3; ++j) {
+            o.m[3 * i + j] = float(double(R[3 * j + i]) / s);
+            c -= double(R[3 * j + i]) * in.translation[j];
+        }
+        o.c[i] = float(c / s);
+    }
+    // world bounds of the unit cube, widened by a relative 1e-6 for rounding
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int corner = 0; corner < 8; ++corner) {
+        const double x[3] = {double(corner & 1), double((corner >> 1) & 1), double((corner >> 2) & 1)};
+        for (int i = 0; i < 3; ++i) {
+            double w = in.translation[i];
+            for (int j = 0; j < 3; ++j) w += double(s) * R[3 * i + j] * x[j];
+            lo[i] = std::min(lo[i], w);
+            hi[i] = std::max(hi[i], w);
+        }
+    }
+    for (int i = 0; i < 3; ++i) {
+        const double pad = 1e-6 * (std::fabs(lo[i]) + std::fabs(hi[i]) + s);
+        o.lo[i] = float(lo[i] - pad);
+        o.hi[i] = float(hi[i] + pad);
+    }
+}
+
+void run_scene(const inrf_instance* objects, int32_t n_objs, int32_t precision, const inrf_camera* camera,
+               float* rgba, float* depth, int32_t* tri, int32_t* obj, void* ws, int64_t ws_bytes, void* stream) {
+    check_precision(precision);
+    require(n_objs >= 0 && n_objs <= kMaxObjects, "n_objects must be in [0, INRF_MAX_OBJECTS]");
+    require(n_objs == 0 || objects != nullptr, "objects is NULL");
+    const CamC cam = make_camera(camera);
+    const int64_t n = int64_t(cam.W) * cam.H;
+    require(rgba != nullptr && ws != nullptr, "rgba and workspace must be set");
+    require((reinterpret_cast<uintptr_t>(ws) & 255) == 0 && (reinterpret_cast<uintptr_t>(rgba) & 15) == 0,
+            "workspace must be 256-byte and rgba 16-byte aligned");
+    const SceneWs L(n, n_objs);
+    if (ws_bytes < L.end)
+        fail(INRF_E_SIZE, "workspace of " + std::to_string(ws_bytes) + " bytes < " + std::to_string(L.end) + " needed");
+    SceneC sc;
+    std::memset(&sc, 0, sizeof(sc));
+    sc.n_objs = n_objs;
+    std::vector<ModelC> models(static_cast<size_t>(n_objs));
+    for (int k = 0; k < n_objs; ++k) {
+        models[size_t(k)] = make_model(objects[k].model, true, true);
+        require(objects[k].model->weights != nullptr, "instance weights must be set");
+        make_object(objects[k], sc.o[k]);
+        sc.o[k].nodes = models[size_t(k)].nodes;
+        sc.o[k].tris = models[size_t(k)].tris;
+        sc.o[k].n_tris = int32_t(models[size_t(k)].n_tris);
+        sc.o[k].stack_depth = models[size_t(k)].stack_depth;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int32_t* counter = ws_at<int32_t>(ws, 0);
+    HitRec* recs = ws_at<HitRec>(ws, L.recs);
+    int2* blk = ws_at<int2>(ws, L.blk);
+    int32_t* offsets = ws_at<int32_t>(ws, L.offsets);
+    int32_t* runs = ws_at<int32_t>(ws, L.runs);
+    int32_t* seg = ws_at<int32_t>(ws, L.seg);
+    const int n_tiles = cam.tiles_x * ((cam.H + kTile - 1) / kTile);
+    const SceneArgs a{rgba, depth, tri, obj, ws_at<HitRec>(ws, L.tmp), blk};
+    hipLaunchKernelGGL(k_trace_scene, dim3(n_tiles), dim3(kThreads), 0, s, sc, cam, a, n_tiles);
+    launch_check("k_trace_scene");
+    if (n_objs == 0) return;
+    const int n_blk = n_objs * n_tiles;
+    const int n_runs = (n_blk + kScanRun - 1) / kScanRun;
+    hipLaunchKernelGGL(k_scan_local, dim3(n_runs), dim3(kScanThreads), 0, s, blk, n_blk, offsets, runs);
+    launch_check("k_scan_local");
+    hipLaunchKernelGGL(k_scan_runs, dim3(1), dim3(kScanThreads), 0, s, runs, n_runs, counter);
+    launch_check("k_scan_runs");
+    hipLaunchKernelGGL(k_compact, dim3(n_blk), dim3(kThreads), 0, s, blk, offsets, runs, a.tmp, recs);
+    launch_check("k_compact");
+    hipLaunchKernelGGL(k_segments, dim3(1), dim3(64), 0, s, offsets, runs, n_tiles, n_objs, counter, seg);
+    launch_check("k_segments");
+    for (int k = 0; k < n_objs; ++k) {
+        const ModelC& c = models[size_t(k)];
+        if (c.table_dtype == INRF_F32) launch_shade<float>(c, precision, recs, seg + k, seg + k + 1, rgba, s);
+        else launch_shade<__half>(c, precision, recs, seg + k, seg + k + 1, rgba, s);
+        launch_check("k_shade");
+    }
 }
 
 }  // namespace
@@ -1036,6 +1173,19 @@ inrf_status inrf_backward(const inrf_model* m, const float* ray_o, const float* 
                           float* d_table, float* d_weights, float* rgba, void* ws, int64_t ws_bytes, void* stream) {
     return guarded("inrf_backward", [&] {
         run_backward(m, ray_o, ray_d, n, d_rgba, d_table, d_weights, rgba, ws, ws_bytes, stream);
+    });
+}
+
+int64_t inrf_scene_workspace_size(int32_t n_objects, int64_t n_rays) {
+    if (n_objects < 0 || n_objects > INRF_MAX_OBJECTS || n_rays < 0) return -1;
+    return SceneWs(n_rays, n_objects).end;
+}
+
+inrf_status inrf_render_scene(const inrf_instance* objects, int32_t n_objects, int32_t precision,
+                              const inrf_camera* cam, float* rgba, float* depth, int32_t* tri, int32_t* object,
+                              void* ws, int64_t ws_bytes, void* stream) {
+    return guarded("inrf_render_scene", [&] {
+        run_scene(objects, n_objects, precision, cam, rgba, depth, tri, object, ws, ws_bytes, stream);
     });
 }
 

@@ -1,0 +1,153 @@
+// Scenes of several objects (each an i-NOLF in its own unit cube, placed by a
+// similarity transform), merged per ray by depth as the paper's frame
+// composer merges objects (Sec. 5).  Included by render.hip after the trace
+// kernels, whose ray generation, packet traversal and record layout it
+// reuses.
+//
+// k_trace_scene: per camera wave, the objects are visited in index order;
+// an object is skipped unless some lane's ray meets its world box before the
+// lane's current closest hit.  A visited object's BVH is traversed as one
+// packet with the ray mapped to object space (the ray parameter t is the same
+// in both spaces, so hits compare directly); a later object replaces a hit
+// only if strictly nearer, so equal t goes to the lower index.  Hit records
+// hold the object-space hit point and unit direction and the object index,
+// and are written per tile grouped by object; the scan and compaction then
+// give one contiguous run of records per object, which the shading kernel
+// of that object processes.
+#pragma once
+
+namespace inrf {
+namespace dev {
+
+constexpr int kMaxObjects = INRF_MAX_OBJECTS;
+
+struct ObjC {
+    float m[9];                 // world -> object, linear part R^T / s (row-major)
+    float c[3];                 // world -> object, offset -R^T t / s
+    float lo[3], hi[3];         // world bounds of the object's unit cube
+    const BvhNode* nodes;
+    const BvhTri* tris;
+    int32_t n_tris, stack_depth;
+};
+
+struct SceneC {
+    int32_t n_objs, pad;
+    ObjC o[kMaxObjects];
+};
+
+struct SceneArgs {
+    float* rgba;     // zero colour of misses
+    float* depth;    // nullable
+    int32_t* tri;    // nullable
+    int32_t* obj;    // nullable
+    HitRec* tmp;     // hit records of tile b at blk[k * n_tiles + b].y, object k
+    int2* blk;       // [n_objs][n_tiles]: (hits of object k in tile b, first record in tmp)
+};
+
+__device__ __forceinline__ float3 xform(const float* m, const float* c, float3 v, bool point) {
+    float3 r = make_float3(m[0] * v.x + m[1] * v.y + m[2] * v.z, m[3] * v.x + m[4] * v.y + m[5] * v.z,
+                           m[6] * v.x + m[7] * v.y + m[8] * v.z);
+    if (point) r = make_float3(r.x + c[0], r.y + c[1], r.z + c[2]);
+    return r;
+}
+
+__global__ __launch_bounds__(kThreads) void k_trace_scene(SceneC sc, CamC cam, SceneArgs a, int n_tiles) {
+    __shared__ int wst[(kThreads / 64) * kBvhMaxStack];
+    __shared__ int s_cnt[kThreads / 64][kMaxObjects];
+    const int lane = __lane_id(), wave = int(threadIdx.x) / 64;
+    const int b = blockIdx.x, tx = b % cam.tiles_x, ty = b / cam.tiles_x;
+    const int row = ty * kTile + 8 * (wave >> 1) + (lane >> 3), col = tx * kTile + 8 * (wave & 1) + (lane & 7);
+    const bool valid = row < cam.H && col < cam.W;
+    const int64_t ray = int64_t(row) * cam.W + col;
+    const int64_t base = int64_t(ty) * kTile * cam.W + int64_t(tx) * kTile * min(kTile, cam.H - ty * kTile);
+    const float sx = ((2.f * (float(col) + 0.5f)) / float(cam.W) - 1.f) * cam.tan_x;
+    const float sy = (1.f - (2.f * (float(row) + 0.5f)) / float(cam.H)) * cam.tan_y;
+    float3 v = make_float3(cam.f[0] + sx * cam.r[0] + sy * cam.u[0], cam.f[1] + sx * cam.r[1] + sy * cam.u[1],
+                           cam.f[2] + sx * cam.r[2] + sy * cam.u[2]);
+    const float inv = 1.f / sqrtf(v.x * v.x + v.y * v.y + v.z * v.z);
+    const float3 d = make_float3(v.x * inv, v.y * inv, v.z * inv);
+    const float3 o = make_float3(cam.o[0], cam.o[1], cam.o[2]);
+    const RayPre Rw = ray_setup(o, d);
+
+    float best_t = INFINITY;
+    int32_t best_i = -1, best_k = -1;
+    for (int k = 0; k < sc.n_objs; ++k) {
+        const ObjC& ob = sc.o[k];
+        float tn;
+        const bool in_box = valid && hit_box(Rw, ob.lo[0], ob.lo[1], ob.lo[2], ob.hi[0], ob.hi[1], ob.hi[2], best_t, tn);
+        if (__ballot(in_box) == 0) continue;
+        const float3 oo = xform(ob.m, ob.c, o, true), dd = xform(ob.m, ob.c, d, false);
+        const RayPre Ro = ray_setup(oo, dd);
+        float t_k = best_t;
+        int32_t i_k = -1;  // an equal t cannot replace the earlier object
+        closest_hit_packet(ob, Ro, in_box, wst + wave * kBvhMaxStack, t_k, i_k);
+        if (i_k >= 0) {
+            best_t = t_k;
+            best_i = i_k;
+            best_k = k;
+        }
+    }
+    const bool hit = best_k >= 0;
+    if (valid) {
+        if (a.depth) a.depth[ray] = best_t;
+        if (a.tri) a.tri[ray] = best_i;
+        if (a.obj) a.obj[ray] = best_k;
+        if (!hit) reinterpret_cast<float4*>(a.rgba)[ray] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    // per-object counts of the tile, then records grouped by object
+    int my_before = 0;  // records of lower objects in this tile, plus those of lower waves for my object
+    uint64_t my_mask = 0;
+    for (int k = 0; k < sc.n_objs; ++k) {
+        const uint64_t mk = __ballot(hit && best_k == k);
+        if (lane == 0) s_cnt[wave][k] = __popcll(mk);
+        if (best_k == k) my_mask = mk;
+    }
+    __syncthreads();
+    int lower_objects = 0;
+    for (int k = 0; k < sc.n_objs; ++k) {
+        int tile_k = 0, waves_before = 0;
+#pragma unroll
+        for (int w = 0; w < kThreads / 64; ++w) {
+            tile_k += s_cnt[w][k];
+            waves_before += w < wave ? s_cnt[w][k] : 0;
+        }
+        if (best_k == k) my_before = lower_objects + waves_before;
+        if (threadIdx.x == 0) a.blk[int64_t(k) * n_tiles + b] = make_int2(tile_k, int(base) + lower_objects);
+        lower_objects += tile_k;
+    }
+    if (hit) {
+        const int64_t pos = base + my_before + __popcll(my_mask & ((uint64_t(1) << lane) - 1));
+        HitRec h;
+        for (int k = 0; k < sc.n_objs; ++k) {  // object-space point and direction of the winner
+            if (best_k != k) continue;
+            const ObjC& ob = sc.o[k];
+            const float3 oo = xform(ob.m, ob.c, o, true), dd = xform(ob.m, ob.c, d, false);
+            const float il = 1.f / sqrtf(dd.x * dd.x + dd.y * dd.y + dd.z * dd.z);
+            h.x = clamp01(oo.x + best_t * dd.x);
+            h.y = clamp01(oo.y + best_t * dd.y);
+            h.z = clamp01(oo.z + best_t * dd.z);
+            h.dx = dd.x * il;
+            h.dy = dd.y * il;
+            h.dz = dd.z * il;
+        }
+        h.out = int32_t(ray);
+        h.pad = best_k;
+        a.tmp[pos] = h;
+    }
+}
+
+// First record of each object's run in the packed list: seg[k] is the packed
+// offset of entry (k, tile 0); seg[n_objs] the total.
+__global__ void k_segments(const int32_t* __restrict__ offsets, const int32_t* __restrict__ runs, int n_tiles,
+                           int n_objs, const int32_t* __restrict__ counter, int32_t* __restrict__ seg) {
+    const int k = threadIdx.x;
+    if (k < n_objs) {
+        const int e = k * n_tiles;
+        seg[k] = offsets[e] + runs[e / kScanRun];
+    } else if (k == n_objs) {
+        seg[k] = *counter;
+    }
+}
+
+}  // namespace dev
+}  // namespace inrf

@@ -344,3 +344,53 @@ def adam_step(param, grad, m, v, step: int, lr: float = 1e-2, beta1: float = 0.9
     s = stream if stream is not None else torch.cuda.current_stream(param.device)
     L.check(L.lib().inrf_adam(L.ptr(param), L.ptr(grad), L.ptr(m), L.ptr(v), n, ctypes.byref(p), L.ptr(param_f16),
                               ctypes.c_void_p(s.cuda_stream)))
+
+
+class Scene:
+    """Several device-resident objects (Renderers) placed in the world by
+    similarity transforms x_world = scale * R @ x_object + t, rendered with
+    inrf_render_scene (nearest hit over the objects, per-object shading)."""
+
+    def __init__(self, renderers, placements):
+        """placements: one (scale, rotation [3, 3], translation [3]) per renderer."""
+        if len(renderers) != len(placements):
+            raise ValueError("one placement per renderer")
+        if len(renderers) > L.MAX_OBJECTS:
+            raise ValueError(f"at most {L.MAX_OBJECTS} objects")
+        self.objects = list(renderers)
+        self.placements = [(float(s), np.asarray(R, np.float32).reshape(3, 3), np.asarray(t, np.float32).reshape(3))
+                           for s, R, t in placements]
+        self._ws = None
+        self.torch = renderers[0].torch if renderers else None
+
+    def instances(self, table: str):
+        arr = (L.InstanceDesc * max(1, len(self.objects)))()
+        for k, (R, (s, rot, t)) in enumerate(zip(self.objects, self.placements)):
+            arr[k].model = ctypes.addressof(R.desc(table))
+            arr[k].scale = s
+            arr[k].rotation[:] = [float(v) for v in rot.reshape(-1)]
+            arr[k].translation[:] = [float(v) for v in t]
+        return arr
+
+    def workspace(self, n_rays: int):
+        import torch
+        need = int(L.lib().inrf_scene_workspace_size(len(self.objects), n_rays))
+        if need < 0:
+            raise ValueError("invalid scene size")
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+        return self._ws
+
+    def render(self, cam, precision="fp32", table="f32", rgba=None, depth=None, tri=None, obj=None, stream=None):
+        import torch
+        H, W = int(cam.height), int(cam.width)
+        if rgba is None:
+            rgba = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
+        ws = self.workspace(H * W)
+        inst = self.instances(table)
+        c = _camera_desc(cam)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        L.check(L.lib().inrf_render_scene(inst, len(self.objects), PRECISIONS[precision], ctypes.byref(c),
+                                          L.ptr(rgba), L.ptr(depth), L.ptr(tri), L.ptr(obj), L.ptr(ws), ws.numel(),
+                                          ctypes.c_void_p(s.cuda_stream)))
+        return rgba

@@ -13,12 +13,14 @@ from .mesh import icosphere, displaced_sphere, quantize_vertices, VERTEX_FRAC_BI
 from .camera import Camera, look_at_camera, fibonacci_cameras, random_cameras
 from .params import xavier_mlp, level_resolutions, feature_values, table_features
 from .batches import random_rays, surface_points, view_rays
-from .workloads import Workload, workload_tiny, workload_object
+from .workloads import (Workload, workload_tiny, workload_object, SceneObject, SceneWorkload, random_rotation,
+                        scene_tiny, scene_objects)
 
 __all__ = [
     "icosphere", "displaced_sphere", "quantize_vertices", "VERTEX_FRAC_BITS",
     "Camera", "look_at_camera", "fibonacci_cameras", "random_cameras",
     "xavier_mlp", "level_resolutions", "feature_values", "table_features",
     "random_rays", "surface_points", "view_rays",
-    "Workload", "workload_tiny", "workload_object",
+    "Workload", "workload_tiny", "workload_object", "SceneObject", "SceneWorkload", "random_rotation",
+    "scene_tiny", "scene_objects",
 ]
