@@ -114,22 +114,19 @@ __device__ __forceinline__ float hit_triangle(const RayPre& R, const float3 v0, 
     float U = Cx * By - Cy * Bx;
     float V = Ax * Cy - Ay * Cx;
     float W = Bx * Ay - By * Ax;
-    if (U == 0.f || V == 0.f || W == 0.f) {
+    if (U == 0.f || V == 0.f || W == 0.f) {  // rare: redo the edge tests exactly
         U = float(double(Cx) * double(By) - double(Cy) * double(Bx));
         V = float(double(Ax) * double(Cy) - double(Ay) * double(Cx));
         W = float(double(Bx) * double(Ay) - double(By) * double(Ax));
     }
-    if ((U < 0.f || V < 0.f || W < 0.f) && (U > 0.f || V > 0.f || W > 0.f)) return INFINITY;
-    float det = U + V + W;
-    if (det == 0.f) return INFINITY;
+    // the rest is select-based: no divergent branches inside a packet
+    const bool outside = (U < 0.f || V < 0.f || W < 0.f) && (U > 0.f || V > 0.f || W > 0.f);
+    const float det = U + V + W;
     const float Az = R.Sz * Akz, Bz = R.Sz * Bkz, Cz = R.Sz * Ckz;
-    float T = U * Az + V * Bz + W * Cz;
-    if (det < 0.f) {
-        T = -T;
-        det = -det;
-    }
-    if (!(T > 0.f)) return INFINITY;
-    return T / det;
+    const float T0 = U * Az + V * Bz + W * Cz;
+    const float T = det < 0.f ? -T0 : T0;
+    const bool ok = !outside && det != 0.f && T > 0.f;
+    return ok ? T * __builtin_amdgcn_rcpf(fabsf(det)) : INFINITY;
 }
 
 // Slab test of one child box for t in [0, tmax]; conservative by 2*gamma(3)
@@ -146,7 +143,7 @@ __device__ __forceinline__ bool hit_box(const RayPre& R, float lx, float ly, flo
 }
 
 __device__ __forceinline__ void leaf(const RayPre& R, const BvhTri* __restrict__ tris, int32_t ref, float& best_t,
-                                     int32_t& best_i) {
+                                     int32_t& best_i, bool active = true) {
     const int32_t code = ~ref;
     const int32_t first = code >> 3, count = code & 7;
     for (int32_t k = 0; k < count; ++k) {
@@ -155,10 +152,9 @@ __device__ __forceinline__ void leaf(const RayPre& R, const BvhTri* __restrict__
         const float t = hit_triangle(R, make_float3(a.x, a.y, a.z), make_float3(b.x, b.y, b.z),
                                      make_float3(c.x, c.y, c.z));
         const int32_t idx = __float_as_int(a.w);
-        if (t < best_t || (t == best_t && t != INFINITY && idx < best_i)) {
-            best_t = t;
-            best_i = idx;
-        }
+        const bool better = active && (t < best_t || (t == best_t && t != INFINITY && idx < best_i));
+        best_t = better ? t : best_t;
+        best_i = better ? idx : best_i;
     }
 }
 
@@ -261,9 +257,7 @@ __device__ void closest_hit_packet(const B& m, const RayPre& R, bool active, int
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c)
-            if (ref[c] < 0 && any[c]) {
-                if (h[c]) leaf(R, m.tris, ref[c], best_t, best_i);
-            }
+            if (ref[c] < 0 && any[c]) leaf(R, m.tris, ref[c], best_t, best_i, h[c]);  // wave-uniform branch
         float d[4];
         int32_t r[4];
 #pragma unroll

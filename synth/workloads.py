@@ -120,7 +120,7 @@ def scene_tiny(n_objects: int = 3, width: int = 64, height: int = 64) -> SceneWo
 def scene_objects(n_objects: int = 12, width: int = 3840, height: int = 2160, freq: int = 40) -> SceneWorkload:
     """Multi-object scene: displaced spheres (20 * freq^2 triangles, own noise,
     features and network each), 10 levels 16..512, scale 0.2..1.0 in a 4^3
-    box; 8 Fibonacci cameras at distance 8 from the box centre."""
+    box; 8 Fibonacci cameras at distance 6 from the box centre."""
     rng = np.random.Generator(np.random.PCG64(SEED_SCENE))
     objs = []
     res = level_resolutions(16, 512, 10)
@@ -131,5 +131,5 @@ def scene_objects(n_objects: int = 12, width: int = 3840, height: int = 2160, fr
                      feature_seed=SEED_FEATURES + 100 * (k + 1))
         s, R, t = _place(rng, 4.0, 0.2, 1.0)
         objs.append(SceneObject(w, s, R, t))
-    cams = fibonacci_cameras(8, 8.0, width, height, center=(2.0, 2.0, 2.0))
+    cams = fibonacci_cameras(8, 6.0, width, height, center=(2.0, 2.0, 2.0))
     return SceneWorkload(f"scene{n_objects}_displaced_sphere_L10_{width}x{height}", objs, cams)
