@@ -261,6 +261,47 @@ def scene_bench(torch, P, frames, W, H):
     return out
 
 
+def single_level_bench(torch, P, frames, W, H, multi_ms):
+    """The paper's single-resolution PSH (one level of N^3, Sec. 4.1) on the
+    same proxy and cameras, FP16 path, against the 16-level shading time."""
+    import synth
+    out = {}
+    for N in (128, 256, 512):
+        w = synth.workload_object(W, H)
+        w.res = [N]
+        w.weights = synth.xavier_mlp(3, w.d_in)
+        R1 = P.Renderer(w.verts, w.tris, w.res, w.weights,
+                        lambda l, lv, w=w: synth.feature_values(w.feature_seed, l, lv.keys, F=w.F),
+                        tables=("f16",), dilate=w.dilate, seed=w.psh_seed)
+        r = run_frames(torch, R1, w.cameras, "fp16", "f16", frames, 3)
+        shade = sum(r["shade_ms"]) / frames
+        out[f"N{N}"] = {"keys": int(len(R1.levels[0].keys)),
+                        "Mrays_per_s": round(W * H * frames / (sum(r["frame_ms"]) / 1e3) / 1e6, 1),
+                        "shade_ms_avg": round(shade, 4),
+                        "shade_vs_16_levels": round(shade / multi_ms, 3)}
+        log(f"single level N={N}: {out[f'N{N}']}")
+        del R1
+    return out
+
+
+def serve_bench(torch, P, R, duration_s, clients=32, rate_hz=30.0):
+    """Serving: `clients` orbiting clients ask for frames at mixed
+    resolutions at Poisson times; requests are admitted in arrival order
+    into batches rendered by one trace and one shading launch."""
+    import synth
+    from paper_2303_04086_amd.serve import Request, Server
+    reqs = [Request(k, t, c) for k, t, c in synth.orbit_requests(clients, duration_s, rate_hz, 13)]
+    out = {"clients": clients, "rate_hz_per_client": rate_hz, "duration_s": duration_s, "requests": len(reqs),
+           "resolutions": "1920x1080, 1280x720, 3840x2160, 800x800 by client"}
+    for prec, table in (("fp16", "f16"), ("fp32", "f32")):
+        S = Server(R, prec, table, pixel_budget=2 * 3840 * 2160)
+        S.run(reqs[: min(len(reqs), 16)])  # warm-up
+        out[prec] = S.run(reqs)
+        log(f"serve {prec}: {out[prec]}")
+        del S
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -278,6 +319,10 @@ def main():
     ap.add_argument("--train-steps", type=int, default=10, help="timed training steps (0: none)")
     ap.add_argument("--train-batch", type=int, default=1 << 18)
     ap.add_argument("--scene-frames", type=int, default=16, help="timed frames of the 12-object scene (0: none)")
+    ap.add_argument("--serve-seconds", type=float, default=0.25,
+                    help="simulated client time of the serving leg (0: none)")
+    ap.add_argument("--single-frames", type=int, default=16,
+                    help="timed frames of the single-resolution PSH variants (0: none)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times), the reference "
                          "for scaling hardware byte counters, and exit")
@@ -334,6 +379,9 @@ def main():
             log(f"mlp {prec}: {mlp[prec]}")
     sweep = sweep_bench(torch, R, w, args.sweep_frames) if args.sweep_frames > 0 else None
     scene = scene_bench(torch, P, args.scene_frames, W, H) if args.scene_frames > 0 else None
+    serve = serve_bench(torch, P, R, args.serve_seconds) if args.serve_seconds > 0 else None
+    single = (single_level_bench(torch, P, args.single_frames, W, H, out["fp16"][1]["shade_ms_avg"])
+              if args.single_frames > 0 else None)
     train = None
     if args.train_steps > 0:
         train = train_bench(torch, R, w, args.train_steps, args.train_batch)
@@ -380,6 +428,8 @@ def main():
         "mlp": mlp or None,
         "sweep": sweep,
         "scene": scene,
+        "single_level": single,
+        "serve": serve,
         "train": train,
         "cpu_baseline": base,
         "source": source_hash(),

@@ -61,6 +61,7 @@ typedef int32_t inrf_status;
 #define INRF_HIDDEN 64   /* width of both hidden layers */
 #define INRF_OUT 4       /* R, G, B, alpha */
 #define INRF_MAX_OBJECTS 16 /* objects of one scene render */
+#define INRF_MAX_CAMERAS 16 /* cameras of one batched render */
 
 /* Thread-local message of the last failed call ("" if none). */
 const char* inrf_last_error(void);
@@ -254,6 +255,17 @@ inrf_status inrf_render_profiled(const inrf_model* m, int32_t precision, const i
 inrf_status inrf_forward(const inrf_model* m, int32_t precision, const float* ray_o, const float* ray_d,
                          int64_t n, float* rgba, float* depth, int32_t* tri, void* ws, int64_t ws_bytes,
                          void* stream);
+
+/* Several cameras in one pass (the requests of several clients, Sec. 6,
+ * traced and shaded together: one trace launch over all their tiles and one
+ * shading launch over all their hit rays).  cams: host array of n_cameras
+ * (1..INRF_MAX_CAMERAS); rgba (and depth, tri if set) hold the images one
+ * after another in camera order, each as inrf_render writes it.  Every
+ * pixel gets exactly the value inrf_render gives it.  ws: at least
+ * inrf_batch_workspace_size(n_cameras, total pixels) bytes. */
+int64_t inrf_batch_workspace_size(int32_t n_cameras, int64_t n_pixels);
+inrf_status inrf_render_batch(const inrf_model* m, int32_t precision, const inrf_camera* cams, int32_t n_cameras,
+                              float* rgba, float* depth, int32_t* tri, void* ws, int64_t ws_bytes, void* stream);
 
 /* Closest hit only: tri (device int32 [n]) and t (device float32 [n]). */
 inrf_status inrf_trace(const inrf_model* m, const float* ray_o, const float* ray_d, int64_t n, int32_t* tri,

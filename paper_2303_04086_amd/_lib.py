@@ -15,6 +15,7 @@ INRF_F32, INRF_F16, INRF_BF16 = 0, 1, 2
 PREC_FP32, PREC_FP16, PREC_BF16 = 0, 1, 2
 MAX_LEVELS, FEATURES, SH_DIM, HIDDEN, OUT = 32, 2, 16, 64, 4
 MAX_OBJECTS = 16
+MAX_CAMERAS = 16
 
 EXPORTED = [
     "inrf_last_error", "inrf_version", "inrf_psh_params_default", "inrf_build_psh", "inrf_build_psh_keys",
@@ -22,7 +23,7 @@ EXPORTED = [
     "inrf_build_bvh", "inrf_bvh_get_info",
     "inrf_bvh_copy", "inrf_bvh_free", "inrf_workspace_size", "inrf_render", "inrf_render_profiled",
     "inrf_forward", "inrf_trace",
-    "inrf_encode", "inrf_mlp", "inrf_scene_workspace_size", "inrf_render_scene", "inrf_backward_workspace_size",
+    "inrf_encode", "inrf_mlp", "inrf_batch_workspace_size", "inrf_render_batch", "inrf_scene_workspace_size", "inrf_render_scene", "inrf_backward_workspace_size",
     "inrf_backward", "inrf_adam",
 ]
 
@@ -106,6 +107,9 @@ def _declare(lib):
         "inrf_trace": (S, [POINTER(ModelDesc), c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
         "inrf_encode": (S, [POINTER(ModelDesc), c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
         "inrf_mlp": (S, [POINTER(ModelDesc), c_int32, c_void_p, c_int64, c_void_p, c_void_p]),
+        "inrf_batch_workspace_size": (c_int64, [c_int32, c_int64]),
+        "inrf_render_batch": (S, [POINTER(ModelDesc), c_int32, POINTER(CameraDesc), c_int32, c_void_p, c_void_p,
+                                  c_void_p, c_void_p, c_int64, c_void_p]),
         "inrf_scene_workspace_size": (c_int64, [c_int32, c_int64]),
         "inrf_render_scene": (S, [POINTER(InstanceDesc), c_int32, c_int32, POINTER(CameraDesc), c_void_p, c_void_p,
                                   c_void_p, c_void_p, c_void_p, c_int64, c_void_p]),

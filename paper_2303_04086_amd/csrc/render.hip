@@ -45,6 +45,16 @@ struct CamC {
     float o[3], r[3], u[3], f[3];
     float tan_y, tan_x;  // tan(fov_y/2) and tan(fov_y/2)*W/H
     int32_t W, H, tiles_x;
+    int32_t tile0;       // first tile of this camera in a batch of cameras
+    int64_t pix0;        // first output pixel of this camera in a batch
+};
+
+// Cameras traced by one launch: tiles of camera j are [c[j].tile0, c[j+1].tile0).
+constexpr int kMaxCameras = INRF_MAX_CAMERAS;
+template <int NCAM>
+struct CamSet {
+    int32_t n, pad;
+    CamC c[NCAM];
 };
 
 struct TraceArgs {
@@ -296,8 +306,8 @@ __device__ void closest_hit_packet(const B& m, const RayPre& R, bool active, int
 // workgroup in lane order to tmp[base ..], base = the index of the
 // workgroup's first ray in the output (tiles of a row band are laid out
 // one after another), with blk[b] = (hits, base).
-template <bool CAMERA>
-__global__ __launch_bounds__(kThreads) void k_trace(ModelC m, CamC cam, TraceArgs a) {
+template <bool CAMERA, int NCAM>
+__global__ __launch_bounds__(kThreads) void k_trace(ModelC m, CamSet<NCAM> cams, TraceArgs a) {
     extern __shared__ int stack[];  // batch: [m.stack_depth][kThreads] per-lane stacks
     __shared__ int wst[(kThreads / 64) * kBvhMaxStack];
     __shared__ int s_cnt[kThreads / 64];
@@ -306,11 +316,15 @@ __global__ __launch_bounds__(kThreads) void k_trace(ModelC m, CamC cam, TraceArg
     bool valid;
     float3 o, d;
     if (CAMERA) {
-        const int tile = blockIdx.x, tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+        int j = 0;  // the camera of this tile (wave-uniform)
+        for (int k = 1; k < NCAM && k < cams.n; ++k)
+            if (int(blockIdx.x) >= cams.c[k].tile0) j = k;
+        const CamC& cam = cams.c[j];
+        const int tile = int(blockIdx.x) - cam.tile0, tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
         const int row = ty * kTile + 8 * (wave >> 1) + (lane >> 3), col = tx * kTile + 8 * (wave & 1) + (lane & 7);
         valid = row < cam.H && col < cam.W;
-        ray = int64_t(row) * cam.W + col;
-        base = int64_t(ty) * kTile * cam.W + int64_t(tx) * kTile * min(kTile, cam.H - ty * kTile);
+        ray = cam.pix0 + int64_t(row) * cam.W + col;
+        base = cam.pix0 + int64_t(ty) * kTile * cam.W + int64_t(tx) * kTile * min(kTile, cam.H - ty * kTile);
         const float sx = ((2.f * (float(col) + 0.5f)) / float(cam.W) - 1.f) * cam.tan_x;
         const float sy = (1.f - (2.f * (float(row) + 0.5f)) / float(cam.H)) * cam.tan_y;
         float3 v = make_float3(cam.f[0] + sx * cam.r[0] + sy * cam.u[0], cam.f[1] + sx * cam.r[1] + sy * cam.u[1],
@@ -663,8 +677,9 @@ int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
 // tiles.
 struct WsLayout {
     int64_t recs, tmp, blk, offsets, runs, end;
-    explicit WsLayout(int64_t n) {
-        const int64_t nb = n / 8 + 2, nr = nb / kScanRun + 1;
+    // extra: 2 more tiles per additional camera of a batch
+    explicit WsLayout(int64_t n, int64_t extra = 0) {
+        const int64_t nb = n / 8 + 2 + extra, nr = nb / kScanRun + 1;
         recs = kWsHeader;
         tmp = align256(recs + n * int64_t(sizeof(HitRec)));
         blk = align256(tmp + n * int64_t(sizeof(HitRec)));
@@ -838,20 +853,22 @@ void record(void* const* events, int i, hipStream_t s) {
 
 // Clears the hit counter, then traces n rays (camera rays when cam is set),
 // writing depth / triangle / zero colour of misses and appending hit records.
-// Launches k_trace, one workgroup per tile (camera) or 256-ray block
+// Launches k_trace, one workgroup per tile (cameras) or 256-ray block
 // (batch); returns the number of workgroups.
-int launch_trace(const ModelC& c, const CamC* cam, const TraceArgs& a, int64_t n, hipStream_t s) {
-    if (cam) {
-        const int n_blk = cam->tiles_x * ((cam->H + kTile - 1) / kTile);
-        hipLaunchKernelGGL(k_trace<true>, dim3(n_blk), dim3(kThreads), 0, s, c, *cam, a);
+template <int NCAM>
+int launch_trace(const ModelC& c, const CamSet<NCAM>* cams, const TraceArgs& a, int64_t n, hipStream_t s) {
+    if (cams) {
+        const CamC& last = cams->c[cams->n - 1];
+        const int n_blk = last.tile0 + last.tiles_x * ((last.H + kTile - 1) / kTile);
+        hipLaunchKernelGGL((k_trace<true, NCAM>), dim3(n_blk), dim3(kThreads), 0, s, c, *cams, a);
         launch_check("k_trace");
         return n_blk;
     }
-    CamC none;
+    CamSet<1> none;
     std::memset(&none, 0, sizeof(none));
     const int n_blk = int((n + kThreads - 1) / kThreads);
     const size_t stack_bytes = size_t(c.stack_depth) * kThreads * sizeof(int);
-    hipLaunchKernelGGL(k_trace<false>, dim3(n_blk), dim3(kThreads), stack_bytes, s, c, none, a);
+    hipLaunchKernelGGL((k_trace<false, 1>), dim3(n_blk), dim3(kThreads), stack_bytes, s, c, none, a);
     launch_check("k_trace");
     return n_blk;
 }
@@ -859,16 +876,17 @@ int launch_trace(const ModelC& c, const CamC* cam, const TraceArgs& a, int64_t n
 // Traces n rays (camera rays when cam is set), writing depth / triangle /
 // zero colour of misses, then packs the hit records into one list in
 // workgroup order and writes its length to the counter.
-void trace_to_hits(const ModelC& c, const CamC* cam, const float* ray_o, const float* ray_d, int64_t n, float* rgba,
-                   float* depth, int32_t* tri, void* ws, hipStream_t s) {
-    const WsLayout L(n);
+template <int NCAM>
+void trace_to_hits(const ModelC& c, const CamSet<NCAM>* cams, const float* ray_o, const float* ray_d, int64_t n,
+                   float* rgba, float* depth, int32_t* tri, void* ws, hipStream_t s) {
+    const WsLayout L(n, cams ? 2 * int64_t(cams->n - 1) : 0);
     int32_t* counter = ws_at<int32_t>(ws, 0);
     HitRec* recs = ws_at<HitRec>(ws, L.recs);
     int2* blk = ws_at<int2>(ws, L.blk);
     int32_t* offsets = ws_at<int32_t>(ws, L.offsets);
     int32_t* runs = ws_at<int32_t>(ws, L.runs);
     TraceArgs a{ray_o, ray_d, n, rgba, depth, tri, ws_at<HitRec>(ws, L.tmp), blk};
-    const int n_blk = launch_trace(c, cam, a, n, s);
+    const int n_blk = launch_trace(c, cams, a, n, s);
     const int n_runs = (n_blk + kScanRun - 1) / kScanRun;
     hipLaunchKernelGGL(k_scan_local, dim3(n_runs), dim3(kScanThreads), 0, s, blk, n_blk, offsets, runs);
     launch_check("k_scan_local");
@@ -878,9 +896,10 @@ void trace_to_hits(const ModelC& c, const CamC* cam, const float* ray_o, const f
     launch_check("k_compact");
 }
 
-void run_path(const inrf_model* m, int32_t precision, const CamC* cam, const float* ray_o, const float* ray_d,
-              int64_t n, float* rgba, float* depth, int32_t* tri, void* ws, int64_t ws_bytes, void* stream,
-              void* const* events = nullptr) {
+template <int NCAM>
+void run_path(const inrf_model* m, int32_t precision, const CamSet<NCAM>* cams, const float* ray_o,
+              const float* ray_d, int64_t n, float* rgba, float* depth, int32_t* tri, void* ws, int64_t ws_bytes,
+              void* stream, void* const* events = nullptr) {
     check_precision(precision);
     const ModelC c = make_model(m, true, true);
     require(m->weights != nullptr, "weights must be set");
@@ -889,14 +908,15 @@ void run_path(const inrf_model* m, int32_t precision, const CamC* cam, const flo
     require(ws != nullptr, "workspace is NULL");
     require((reinterpret_cast<uintptr_t>(ws) & 15) == 0 && (reinterpret_cast<uintptr_t>(rgba) & 15) == 0,
             "rgba and workspace must be 16-byte aligned");
-    if (ws_bytes < inrf_workspace_size(n))
-        fail(INRF_E_SIZE, "workspace of " + std::to_string(ws_bytes) + " bytes < " +
-                              std::to_string(inrf_workspace_size(n)) + " needed");
+    const WsLayout L(n, cams ? 2 * int64_t(cams->n - 1) : 0);
+    if (ws_bytes < L.end)
+        fail(INRF_E_SIZE, "workspace of " + std::to_string(ws_bytes) + " bytes < " + std::to_string(L.end) +
+                              " needed");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int32_t* counter = ws_at<int32_t>(ws, 0);
-    const HitRec* recs = ws_at<HitRec>(ws, WsLayout(n).recs);
+    const HitRec* recs = ws_at<HitRec>(ws, L.recs);
     record(events, 0, s);
-    trace_to_hits(c, cam, ray_o, ray_d, n, rgba, depth, tri, ws, s);
+    trace_to_hits(c, cams, ray_o, ray_d, n, rgba, depth, tri, ws, s);
     record(events, 1, s);
     if (c.table_dtype == INRF_F32) launch_shade<float>(c, precision, recs, nullptr, counter, rgba, s);
     else launch_shade<__half>(c, precision, recs, nullptr, counter, rgba, s);
@@ -958,7 +978,7 @@ void run_backward(const inrf_model* m, const float* ray_o, const float* ray_d, i
     const int32_t* counter = ws_at<int32_t>(ws, 0);
     const HitRec* recs = ws_at<HitRec>(ws, WsLayout(n).recs);
     float* partial = ws_at<float>(ws, WsLayout(n).end);
-    trace_to_hits(c, nullptr, ray_o, ray_d, n, rgba, nullptr, nullptr, ws, s);
+    trace_to_hits<1>(c, nullptr, ray_o, ray_d, n, rgba, nullptr, nullptr, ws, s);
 #define INRF_BACK(LPG)                                                                                   \
     do {                                                                                                \
         if (c.table_dtype == INRF_F32)                                                                  \
@@ -993,6 +1013,8 @@ CamC make_camera(const inrf_camera* cam) {
     c.W = cam->width;
     c.H = cam->height;
     c.tiles_x = (cam->width + kTile - 1) / kTile;
+    c.tile0 = 0;
+    c.pix0 = 0;
     return c;
 }
 
@@ -1130,8 +1152,9 @@ int64_t inrf_workspace_size(int64_t n_rays) {
 inrf_status inrf_render(const inrf_model* m, int32_t precision, const inrf_camera* cam, float* rgba, float* depth,
                         int32_t* tri, void* ws, int64_t ws_bytes, void* stream) {
     return guarded("inrf_render", [&] {
-        const dev::CamC c = make_camera(cam);
-        run_path(m, precision, &c, nullptr, nullptr, int64_t(c.W) * c.H, rgba, depth, tri, ws, ws_bytes, stream);
+        const dev::CamSet<1> cs{1, 0, {make_camera(cam)}};
+        run_path(m, precision, &cs, nullptr, nullptr, int64_t(cs.c[0].W) * cs.c[0].H, rgba, depth, tri, ws, ws_bytes,
+                 stream);
     });
 }
 
@@ -1139,9 +1162,35 @@ inrf_status inrf_render_profiled(const inrf_model* m, int32_t precision, const i
                                  float* depth, int32_t* tri, void* ws, int64_t ws_bytes, void* stream,
                                  void* const* events) {
     return guarded("inrf_render_profiled", [&] {
-        const dev::CamC c = make_camera(cam);
-        run_path(m, precision, &c, nullptr, nullptr, int64_t(c.W) * c.H, rgba, depth, tri, ws, ws_bytes, stream,
-                 events);
+        const dev::CamSet<1> cs{1, 0, {make_camera(cam)}};
+        run_path(m, precision, &cs, nullptr, nullptr, int64_t(cs.c[0].W) * cs.c[0].H, rgba, depth, tri, ws, ws_bytes,
+                 stream, events);
+    });
+}
+
+int64_t inrf_batch_workspace_size(int32_t n_cameras, int64_t n_pixels) {
+    if (n_cameras < 1 || n_cameras > INRF_MAX_CAMERAS || n_pixels < 0) return -1;
+    return WsLayout(n_pixels, 2 * int64_t(n_cameras - 1)).end;
+}
+
+inrf_status inrf_render_batch(const inrf_model* m, int32_t precision, const inrf_camera* cams, int32_t n_cameras,
+                              float* rgba, float* depth, int32_t* tri, void* ws, int64_t ws_bytes, void* stream) {
+    return guarded("inrf_render_batch", [&] {
+        require(n_cameras >= 1 && n_cameras <= INRF_MAX_CAMERAS, "n_cameras must be in [1, INRF_MAX_CAMERAS]");
+        require(cams != nullptr, "cameras is NULL");
+        dev::CamSet<dev::kMaxCameras> cs;
+        std::memset(&cs, 0, sizeof(cs));
+        cs.n = n_cameras;
+        int64_t pix = 0, tiles = 0;
+        for (int j = 0; j < n_cameras; ++j) {
+            cs.c[j] = make_camera(&cams[j]);
+            cs.c[j].tile0 = int32_t(tiles);
+            cs.c[j].pix0 = pix;
+            pix += int64_t(cs.c[j].W) * cs.c[j].H;
+            tiles += int64_t(cs.c[j].tiles_x) * ((cs.c[j].H + dev::kTile - 1) / dev::kTile);
+            require(pix <= (int64_t(1) << 31) - 1, "batch too large (2^31 pixels)");
+        }
+        run_path(m, precision, &cs, nullptr, nullptr, pix, rgba, depth, tri, ws, ws_bytes, stream);
     });
 }
 
@@ -1150,7 +1199,7 @@ inrf_status inrf_forward(const inrf_model* m, int32_t precision, const float* ra
     return guarded("inrf_forward", [&] {
         require(n >= 0 && n <= (int64_t(1) << 31) - 1, "n must be in [0, 2^31)");
         require(n == 0 || (ray_o && ray_d), "ray buffers are NULL");
-        run_path(m, precision, nullptr, ray_o, ray_d, n, rgba, depth, tri, ws, ws_bytes, stream);
+        run_path<1>(m, precision, nullptr, ray_o, ray_d, n, rgba, depth, tri, ws, ws_bytes, stream);
     });
 }
 
@@ -1191,7 +1240,7 @@ inrf_status inrf_trace(const inrf_model* m, const float* ray_o, const float* ray
         require(n == 0 || (ray_o && ray_d && tri && t), "NULL buffer");
         if (n == 0) return;
         const dev::TraceArgs a{ray_o, ray_d, n, nullptr, t, tri, nullptr, nullptr};  // no records
-        launch_trace(c, nullptr, a, n, reinterpret_cast<hipStream_t>(stream));
+        launch_trace<1>(c, nullptr, a, n, reinterpret_cast<hipStream_t>(stream));
     });
 }
 

@@ -250,6 +250,33 @@ class Renderer:
             L.check(L.lib().inrf_render_profiled(*args, arr))
         return rgba
 
+    def render_batch(self, cams, precision="fp32", table="f32", rgba=None, depth=None, tri=None, stream=None):
+        """Render several cameras in one pass (inrf_render_batch).  Returns
+        the flat [sum(W*H), 4] RGBA buffer and the list of per-camera
+        [H, W, 4] views into it."""
+        torch = self.torch
+        cams = list(cams)
+        if not 1 <= len(cams) <= L.MAX_CAMERAS:
+            raise ValueError(f"1..{L.MAX_CAMERAS} cameras per batch")
+        sizes = [int(c.width) * int(c.height) for c in cams]
+        n = sum(sizes)
+        if rgba is None:
+            rgba = torch.empty((n, 4), dtype=torch.float32, device=self.device)
+        need = int(L.lib().inrf_batch_workspace_size(len(cams), n))
+        if need < 0:
+            raise ValueError("invalid batch")
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        arr = (L.CameraDesc * len(cams))(*[_camera_desc(c) for c in cams])
+        L.check(L.lib().inrf_render_batch(ctypes.byref(self.desc(table)), PRECISIONS[precision], arr, len(cams),
+                                          L.ptr(rgba), L.ptr(depth), L.ptr(tri), L.ptr(self._ws), self._ws.numel(),
+                                          self._stream(stream)))
+        views, off = [], 0
+        for c, k in zip(cams, sizes):
+            views.append(rgba[off:off + k].view(int(c.height), int(c.width), 4))
+            off += k
+        return rgba, views
+
     def hit_count(self) -> int:
         """Hit rays of the last render/forward (reads the workspace counter)."""
         return int(self._ws[:4].view(self.torch.int32).item())

@@ -133,6 +133,23 @@ def test_mlp_odd_levels_and_unaligned_inputs(n_levels):
             assert np.abs(got - want).max() <= tol, (prec, x.data_ptr() % 16)
 
 
+@pytest.mark.parametrize("N", [64, 40])
+def test_single_resolution_model(N):
+    """One level (the paper's single-resolution PSH): the LPG = 1 kernels."""
+    w = synth.workload_tiny()
+    w.res = [N]
+    w.weights = synth.xavier_mlp(9, w.d_in)
+    R1 = make_renderer(w, tables=("f32", "f16"), kind="uniform", sigma=0.5)
+    cam = w.cameras[0]
+    tri = torch.empty(cam.height * cam.width, dtype=torch.int32, device="cuda")
+    got = R1.render(cam, "fp32", "f32", tri=tri).cpu().numpy().reshape(-1, 4)
+    got16 = R1.render(cam, "fp16", "f16").cpu().numpy().reshape(-1, 4)
+    ora = oracle.render_camera(oracle.Model.from_workload(w, kind="uniform", sigma=0.5), cam)
+    agree = compare_hits(tri.cpu().numpy(), ora)
+    assert np.abs(got[agree] - ora["rgba"][agree]).max() <= 1e-4   # loud features, N <= 64
+    assert np.abs(got16[agree] - ora["rgba"][agree]).max() <= 2e-3
+
+
 def test_render_full_frame_fp32(tiny, R, tiny_oracle):
     cam = tiny.cameras[0]
     depth = torch.empty(cam.height * cam.width, device="cuda")
