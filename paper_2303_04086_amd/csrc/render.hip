@@ -1,19 +1,22 @@
 // Device entry points of libinrf: closest-hit trace, position encoding, the
 // network alone, and the fused per-ray path (inrf_render / inrf_forward).
 //
-// A frame is four launches on the caller's stream:
+// A frame is five launches on the caller's stream:
 //   k_trace   one ray per lane: generate (camera) or load (batch) the ray,
 //             closest hit through the BVH with a watertight triangle test
 //             (a camera wave traverses as one packet), write depth / triangle
 //             / zero colour for misses, and write the hit records (hit point,
-//             unit direction, output index) of each workgroup in lane order;
-//   k_scan, k_compact  pack the records into one list in workgroup order
-//             (deterministic) and count them;
+//             unit direction, output index) of each tile in lane order;
+//   k_scan_local, k_scan_runs, k_compact  pack the records into one list in
+//             tile order (deterministic) and count them;
 //   k_shade   persistent waves over the packed hits: multi-level PSH gather
 //             with trilinear blend, SH16 of the direction, the MLP on matrix
 //             cores, sigmoid, colour write.
 // Each ray's colour depends only on that ray; the packed order fixes which
 // rays share a wave (it matters only to sums over rays, e.g. gradients).
+// The same kernels serve batches of cameras (inrf_render_batch), ray batches
+// (inrf_forward), scenes of several objects (scene_device.hpp) and the
+// gradient (backward_device.hpp).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -85,9 +88,9 @@ __device__ __forceinline__ RayPre ray_setup(float3 o, float3 d) {
     // slab reciprocals: a zero component becomes +-1e-30 so that a ray lying
     // in a slab's boundary plane gives 0 * 1e30 = 0 instead of 0 * inf = NaN
     const float tiny = 1e-30f;
-    R.inv = make_float3(1.f / (fabsf(d.x) < tiny ? copysignf(tiny, d.x) : d.x),
-                        1.f / (fabsf(d.y) < tiny ? copysignf(tiny, d.y) : d.y),
-                        1.f / (fabsf(d.z) < tiny ? copysignf(tiny, d.z) : d.z));
+    R.inv = make_float3(__builtin_amdgcn_rcpf(fabsf(d.x) < tiny ? copysignf(tiny, d.x) : d.x),
+                        __builtin_amdgcn_rcpf(fabsf(d.y) < tiny ? copysignf(tiny, d.y) : d.y),
+                        __builtin_amdgcn_rcpf(fabsf(d.z) < tiny ? copysignf(tiny, d.z) : d.z));
     const float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
     int kz = 0;
     if (ay > ax) kz = 1;
@@ -102,10 +105,10 @@ __device__ __forceinline__ RayPre ray_setup(float3 o, float3 d) {
     R.kx = kx;
     R.ky = ky;
     R.kz = kz;
-    const float dz = comp(d, kz);
-    R.Sx = comp(d, kx) / dz;
-    R.Sy = comp(d, ky) / dz;
-    R.Sz = 1.f / dz;
+    const float rz = __builtin_amdgcn_rcpf(comp(d, kz));  // the shear only needs to be the same for every triangle
+    R.Sx = comp(d, kx) * rz;
+    R.Sy = comp(d, ky) * rz;
+    R.Sz = rz;
     return R;
 }
 
@@ -139,8 +142,11 @@ __device__ __forceinline__ float hit_triangle(const RayPre& R, const float3 v0, 
     return ok ? T * __builtin_amdgcn_rcpf(fabsf(det)) : INFINITY;
 }
 
-// Slab test of one child box for t in [0, tmax]; conservative by 2*gamma(3)
-// (Ize 2013) so that rounding never rejects a box a ray touches.
+// Slab test of one child box for t in [0, tmax]; conservative so that
+// rounding never rejects a box a ray touches: each slab distance
+// (l - o) * rcp(d) carries a relative error below 2^-22 (one rounding of the
+// difference, the reciprocal's 1 ulp, one rounding of the product), so
+// comparing t_near <= t_far * (1 + 2^-20) is safe (cf. Ize 2013).
 __device__ __forceinline__ bool hit_box(const RayPre& R, float lx, float ly, float lz, float hx, float hy, float hz,
                                         float tmax, float& tnear) {
     const float t0x = (lx - R.o.x) * R.inv.x, t1x = (hx - R.o.x) * R.inv.x;
@@ -149,7 +155,7 @@ __device__ __forceinline__ bool hit_box(const RayPre& R, float lx, float ly, flo
     const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.f));
     const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
     tnear = tn;
-    return tn <= tf * 1.00000024f;
+    return tn <= tf * 1.00000095f;
 }
 
 __device__ __forceinline__ void leaf(const RayPre& R, const BvhTri* __restrict__ tris, int32_t ref, float& best_t,
