@@ -284,20 +284,48 @@ def single_level_bench(torch, P, frames, W, H, multi_ms):
     return out
 
 
+def pipelined_bench(torch, P, R, cams, steps, warmup):
+    """Frames of the headline workload with two in flight on two streams
+    (FramePipeline): the trace of one frame overlaps the shading of the one
+    before.  Whole-run throughput: all frames between two synchronizations."""
+    W, H = cams[0].width, cams[0].height
+    out = {"frames_in_flight": 2, "frames": steps}
+    for prec, table in (("fp16", "f16"), ("fp32", "f32")):
+        pipe = P.FramePipeline(R, depth=2)
+        bufs = [torch.empty((H, W, 4), dtype=torch.float32, device="cuda") for _ in range(2)]
+        for i in range(warmup):
+            pipe.submit(cams[i % len(cams)], prec, table, rgba=bufs[i % 2])
+        pipe.wait()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            pipe.submit(cams[i % len(cams)], prec, table, rgba=bufs[i % 2])
+        pipe.wait()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[prec] = {"Mrays_per_s": round(steps * W * H / dt / 1e6, 1), "ms_per_frame": round(dt / steps * 1e3, 4)}
+        log(f"pipelined {prec}: {out[prec]}")
+        del pipe
+    return out
+
+
 def serve_bench(torch, P, R, duration_s, clients=32, rate_hz=30.0):
     """Serving: `clients` orbiting clients ask for frames at mixed
     resolutions at Poisson times; requests are admitted in arrival order
-    into batches rendered by one trace and one shading launch."""
+    into batches rendered by one trace and one shading launch, two batches
+    in flight.  Run in real time, then with every request released at once
+    (saturated: aggregate throughput)."""
     import synth
     from paper_2303_04086_amd.serve import Request, Server
     reqs = [Request(k, t, c) for k, t, c in synth.orbit_requests(clients, duration_s, rate_hz, 13)]
     out = {"clients": clients, "rate_hz_per_client": rate_hz, "duration_s": duration_s, "requests": len(reqs),
-           "resolutions": "1920x1080, 1280x720, 3840x2160, 800x800 by client"}
+           "resolutions": "1920x1080, 1280x720, 3840x2160, 800x800 by client", "in_flight": 2}
     for prec, table in (("fp16", "f16"), ("fp32", "f32")):
         S = Server(R, prec, table, pixel_budget=2 * 3840 * 2160)
-        S.run(reqs[: min(len(reqs), 16)])  # warm-up
+        S.run(reqs[: min(len(reqs), 16)], time_scale=0.0)  # warm-up
         out[prec] = S.run(reqs)
-        log(f"serve {prec}: {out[prec]}")
+        out[prec + "_saturated"] = S.run(reqs, time_scale=0.0)
+        log(f"serve {prec}: {out[prec]}; saturated {out[prec + '_saturated']}")
         del S
     return out
 
@@ -321,6 +349,8 @@ def main():
     ap.add_argument("--scene-frames", type=int, default=16, help="timed frames of the 12-object scene (0: none)")
     ap.add_argument("--serve-seconds", type=float, default=0.25,
                     help="simulated client time of the serving leg (0: none)")
+    ap.add_argument("--pipelined-frames", type=int, default=100,
+                    help="frames of the two-in-flight throughput leg (0: none)")
     ap.add_argument("--single-frames", type=int, default=16,
                     help="timed frames of the single-resolution PSH variants (0: none)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -380,6 +410,8 @@ def main():
     sweep = sweep_bench(torch, R, w, args.sweep_frames) if args.sweep_frames > 0 else None
     scene = scene_bench(torch, P, args.scene_frames, W, H) if args.scene_frames > 0 else None
     serve = serve_bench(torch, P, R, args.serve_seconds) if args.serve_seconds > 0 else None
+    piped = (pipelined_bench(torch, P, R, w.cameras, args.pipelined_frames, args.warmup)
+             if args.pipelined_frames > 0 else None)
     single = (single_level_bench(torch, P, args.single_frames, W, H, out["fp16"][1]["shade_ms_avg"])
               if args.single_frames > 0 else None)
     train = None
@@ -430,6 +462,7 @@ def main():
         "scene": scene,
         "single_level": single,
         "serve": serve,
+        "pipelined": piped,
         "train": train,
         "cpu_baseline": base,
         "source": source_hash(),

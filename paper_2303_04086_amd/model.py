@@ -232,14 +232,16 @@ class Renderer:
 
     # -- calls -------------------------------------------------------------
     def render(self, cam, precision="fp32", table="f32", rgba=None, depth=None, tri=None, stream=None,
-               events=None):
+               events=None, ws=None):
         """Render one camera.  `events`: optional three recorded
-        torch.cuda.Event objects marking trace start, shading start and end."""
+        torch.cuda.Event objects marking trace start, shading start and end.
+        `ws`: optional uint8 workspace of the caller (frames in flight on
+        different streams need one each); else the renderer's own."""
         torch = self.torch
         n = int(cam.width) * int(cam.height)
         if rgba is None:
             rgba = torch.empty((int(cam.height), int(cam.width), 4), dtype=torch.float32, device=self.device)
-        ws = self.workspace(n)
+        ws = self.workspace(n) if ws is None else ws
         c = _camera_desc(cam)
         args = (ctypes.byref(self.desc(table)), PRECISIONS[precision], ctypes.byref(c), L.ptr(rgba), L.ptr(depth),
                 L.ptr(tri), L.ptr(ws), ws.numel(), self._stream(stream))
@@ -250,10 +252,11 @@ class Renderer:
             L.check(L.lib().inrf_render_profiled(*args, arr))
         return rgba
 
-    def render_batch(self, cams, precision="fp32", table="f32", rgba=None, depth=None, tri=None, stream=None):
+    def render_batch(self, cams, precision="fp32", table="f32", rgba=None, depth=None, tri=None, stream=None,
+                     ws=None):
         """Render several cameras in one pass (inrf_render_batch).  Returns
         the flat [sum(W*H), 4] RGBA buffer and the list of per-camera
-        [H, W, 4] views into it."""
+        [H, W, 4] views into it.  `ws` as for render()."""
         torch = self.torch
         cams = list(cams)
         if not 1 <= len(cams) <= L.MAX_CAMERAS:
@@ -265,11 +268,13 @@ class Renderer:
         need = int(L.lib().inrf_batch_workspace_size(len(cams), n))
         if need < 0:
             raise ValueError("invalid batch")
-        if self._ws is None or self._ws.numel() < need:
-            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        if ws is None:
+            if self._ws is None or self._ws.numel() < need:
+                self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+            ws = self._ws
         arr = (L.CameraDesc * len(cams))(*[_camera_desc(c) for c in cams])
         L.check(L.lib().inrf_render_batch(ctypes.byref(self.desc(table)), PRECISIONS[precision], arr, len(cams),
-                                          L.ptr(rgba), L.ptr(depth), L.ptr(tri), L.ptr(self._ws), self._ws.numel(),
+                                          L.ptr(rgba), L.ptr(depth), L.ptr(tri), L.ptr(ws), ws.numel(),
                                           self._stream(stream)))
         views, off = [], 0
         for c, k in zip(cams, sizes):
@@ -352,6 +357,55 @@ class Renderer:
         L.check(L.lib().inrf_backward(ctypes.byref(self.desc(table)), L.ptr(o), L.ptr(d), n, L.ptr(d_rgba),
                                       L.ptr(d_table), L.ptr(d_weights), L.ptr(rgba), L.ptr(ws), ws.numel(),
                                       self._stream(stream)))
+
+
+class FramePipeline:
+    """Frames in flight on `depth` streams of default priority, each with a
+    workspace of its own.  A frame's trace (ALU-bound) then overlaps the
+    shading of the frame before it (bound by gathers from HBM), which
+    raises throughput; every frame's pixels are those of a lone render.
+    submit() returns the frame's RGBA buffer (the event recorded after the
+    frame is in `events`); wait() makes the caller's current stream wait
+    for every submitted frame."""
+
+    def __init__(self, renderer, depth: int = 2):
+        torch = renderer.torch
+        self.R, self.torch = renderer, torch
+        self.streams = [torch.cuda.Stream(device=renderer.device) for _ in range(int(depth))]
+        self.ws = [None] * int(depth)
+        self.events = [None] * int(depth)
+        self.k = 0
+
+    def _workspace(self, slot: int, need: int):
+        if self.ws[slot] is None or self.ws[slot].numel() < need:
+            # the slot's stream may still use the old buffer: let it drain first
+            self.streams[slot].synchronize()
+            self.ws[slot] = self.torch.empty(need, dtype=self.torch.uint8, device=self.R.device)
+        return self.ws[slot]
+
+    def submit(self, cam, precision="fp16", table="f16", rgba=None, depth=None, tri=None):
+        torch = self.torch
+        slot = self.k % len(self.streams)
+        self.k += 1
+        s = self.streams[slot]
+        n = int(cam.width) * int(cam.height)
+        ws = self._workspace(slot, int(L.lib().inrf_workspace_size(n)))
+        if rgba is None:
+            rgba = torch.empty((int(cam.height), int(cam.width), 4), dtype=torch.float32, device=self.R.device)
+        s.wait_stream(torch.cuda.current_stream(self.R.device))  # outputs allocated / reused by the caller
+        for t in (rgba, depth, tri):
+            if t is not None:
+                t.record_stream(s)
+        self.R.render(cam, precision, table, rgba=rgba, depth=depth, tri=tri, stream=s, ws=ws)
+        ev = torch.cuda.Event()
+        ev.record(s)
+        self.events[slot] = ev
+        return rgba
+
+    def wait(self):
+        cur = self.torch.cuda.current_stream(self.R.device)
+        for s in self.streams:
+            cur.wait_stream(s)
 
 
 def adam_step(param, grad, m, v, step: int, lr: float = 1e-2, beta1: float = 0.9, beta2: float = 0.99,

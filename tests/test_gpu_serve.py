@@ -67,6 +67,56 @@ def test_server_serves_every_request(R):
     assert max(checked) > 1  # batches of several requests were compared
 
 
+def test_server_overlap_and_saturation(R):
+    """Two batches in flight and all requests released at once (the
+    saturated case): every request is served and its image equals a lone
+    render; one batch in flight gives the same images."""
+    from paper_2303_04086_amd.serve import Request, Server
+    reqs = [Request(k, t, c) for k, t, c in
+            synth.orbit_requests(6, 0.05, 200.0, 5, resolutions=((64, 64), (48, 32), (100, 40)))]
+    for in_flight in (2, 1):
+        S = Server(R, "fp16", "f16", pixel_budget=2 * 64 * 64, max_batch=4, in_flight=in_flight,
+                   max_request_pixels=100 * 40)
+        seen = []
+
+        def check(batch, views):
+            for r, v in zip(batch, views):
+                assert torch.equal(v, R.render(r.camera, "fp16", "f16"))
+            seen.extend(r.client for r in batch)
+
+        out = S.run(reqs, on_batch=check, time_scale=0.0)
+        assert out["requests"] == len(reqs) == len(seen) and out["in_flight"] == in_flight
+        assert out["mean_batch"] > 1
+
+
+def test_frame_pipeline_matches_lone_renders(R):
+    import paper_2303_04086_amd as P
+    cams = _cams()
+    pipe = P.FramePipeline(R, depth=2)
+    outs = []
+    for c in cams + cams:
+        k = c.width * c.height
+        d = torch.empty(k, device="cuda")
+        t = torch.empty(k, dtype=torch.int32, device="cuda")
+        outs.append((c, pipe.submit(c, "fp16", "f16", depth=d, tri=t), d, t))
+    rgbas = []
+    pipe2 = P.FramePipeline(R, depth=2)
+    for c in cams:
+        rgbas.append(torch.empty((c.height, c.width, 4), device="cuda"))
+        pipe2.submit(c, "fp32", "f32", rgba=rgbas[-1])
+    pipe.wait()
+    pipe2.wait()
+    torch.cuda.synchronize()
+    for c, x, d, t in outs:
+        d1 = torch.empty_like(d)
+        t1 = torch.empty_like(t)
+        ref = R.render(c, "fp16", "f16", depth=d1, tri=t1)
+        torch.cuda.synchronize()
+        assert torch.equal(x, ref) and torch.equal(d, d1) and torch.equal(t, t1)
+    for c, x in zip(cams, rgbas):
+        assert torch.equal(x, R.render(c, "fp32", "f32"))
+
+
 def test_batch_limits(R):
     import ctypes
     import paper_2303_04086_amd as P
