@@ -15,6 +15,7 @@ from .params import xavier_mlp, level_resolutions, feature_values, table_feature
 from .batches import random_rays, surface_points, view_rays
 from .workloads import (Workload, workload_tiny, workload_object, SceneObject, SceneWorkload, random_rotation,
                         scene_tiny, scene_objects)
+from .nolf import NolfWorkload, make_nolf, nolf_tiny, nolf_object
 
 __all__ = [
     "icosphere", "displaced_sphere", "quantize_vertices", "VERTEX_FRAC_BITS",
@@ -22,5 +23,5 @@ __all__ = [
     "xavier_mlp", "level_resolutions", "feature_values", "table_features",
     "random_rays", "surface_points", "view_rays",
     "Workload", "workload_tiny", "workload_object", "SceneObject", "SceneWorkload", "random_rotation",
-    "scene_tiny", "scene_objects",
+    "scene_tiny", "scene_objects", "NolfWorkload", "make_nolf", "nolf_tiny", "nolf_object",
 ]
