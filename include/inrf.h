@@ -317,6 +317,50 @@ inrf_status inrf_render_scene(const inrf_instance* objects, int32_t n_objects, i
                               void* ws, int64_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * The paper's own i-NOLF form (Sec. 4.2): the hit point comes from a march
+ * through cached density texture cubes (Eq. 4, the sample of largest
+ * weight), the summed weights (coarse opacity alpha_c) are a further input
+ * of the network, which returns the specular colour c_s and the opacity,
+ * and cached diffuse texture cubes give the diffuse colour c_d and the
+ * specular tint t at the hit: colour = c_d + t * c_s (Eq. 6-7).
+ * ---------------------------------------------------------------------- */
+
+/* Texture cubes: a base grid of b^3 cells, each holding the index of a small
+ * dense cube of (r+1)^3 vertex values over the cell, or a negative value
+ * (empty: density 0).  The value at x in [0,1]^3 is the trilinear blend of
+ *   g = b x, c = min(floor(g), b-1), u = (g - c) r, p = min(floor(u), r-1)
+ * over the cube's vertices p + {0,1}^3.  Density and diffuse cubes share the
+ * index.  All pointers are caller-owned device memory. */
+typedef struct inrf_cubes {
+    int32_t base_res;      /* b: a power of two in [1, 1024] */
+    int32_t cube_res;      /* r: a power of two in [1, 64] */
+    const int32_t* index;  /* [b^3], cell (cz*b + cy)*b + cx; entries >= n_cubes read the last cube */
+    const void* density;   /* FP16 [n_cubes][(r+1)^3], vertex (i, j, k) at (k*(r+1) + j)*(r+1) + i */
+    const void* diffuse;   /* FP16 [n_cubes][(r+1)^3][4]: diffuse R, G, B, tint; 8-byte aligned */
+    int64_t n_cubes;       /* >= 1 */
+    float step;            /* march step in object units, in [1e-6, 1] (e.g. sqrt(3)/1024) */
+    float t_stop;          /* the march ends once transmittance falls below this, in (0, 1) (e.g. 1e-4) */
+    float w_min;           /* a ray hits if its largest sample weight is at least this, >= 0 (e.g. 1e-4) */
+    int32_t pad;
+} inrf_cubes;
+
+/* Render one camera with the i-NOLF form.  The ray (unit direction) is
+ * marched inside [0,1]^3 at t_in + (j + 1/2) step; each sample's density s
+ * gives alpha = 1 - exp(-s step), weight w = T alpha and T *= exp(-s step);
+ * the march ends after the first sample whose T falls below t_stop.  The
+ * hit is the sample of largest weight (the first on ties) if that weight is
+ * at least w_min, else the ray misses.  m supplies the level tables and the
+ * weights, whose first layer takes d_in = 2L + 17 inputs: the encoding,
+ * SH16 of the direction, then alpha_c; its proxy fields are ignored; at most
+ * 8 levels.  rgba (16-byte aligned, [height*width][4]): hits
+ * (c_d + t c_s, alpha), misses 0.  depth (nullable): t of the hit sample,
+ * +inf on a miss.  alpha_c (nullable): the summed weights of every ray.
+ * ws: 256-byte aligned, at least inrf_workspace_size(width*height) bytes. */
+inrf_status inrf_render_nolf(const inrf_model* m, const inrf_cubes* cubes, int32_t precision,
+                             const inrf_camera* cam, float* rgba, float* depth, float* alpha_c, void* ws,
+                             int64_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Gradient (training, Sec. 4.2 with the loss of Eq. 8).
  * ---------------------------------------------------------------------- */
 

@@ -24,7 +24,7 @@ EXPORTED = [
     "inrf_bvh_copy", "inrf_bvh_free", "inrf_workspace_size", "inrf_render", "inrf_render_profiled",
     "inrf_forward", "inrf_trace",
     "inrf_encode", "inrf_mlp", "inrf_batch_workspace_size", "inrf_render_batch", "inrf_scene_workspace_size", "inrf_render_scene", "inrf_backward_workspace_size",
-    "inrf_backward", "inrf_adam",
+    "inrf_backward", "inrf_adam", "inrf_render_nolf",
 ]
 
 
@@ -69,6 +69,12 @@ class CameraDesc(ctypes.Structure):
 class InstanceDesc(ctypes.Structure):
     _fields_ = [("model", ctypes.c_void_p), ("scale", ctypes.c_float), ("rotation", ctypes.c_float * 9),
                 ("translation", ctypes.c_float * 3)]
+
+
+class CubesDesc(ctypes.Structure):
+    _fields_ = [("base_res", c_int32), ("cube_res", c_int32), ("index", ctypes.c_void_p),
+                ("density", ctypes.c_void_p), ("diffuse", ctypes.c_void_p), ("n_cubes", c_int64),
+                ("step", ctypes.c_float), ("t_stop", ctypes.c_float), ("w_min", ctypes.c_float), ("pad", c_int32)]
 
 
 class AdamParams(ctypes.Structure):
@@ -118,6 +124,8 @@ def _declare(lib):
                               c_void_p, c_void_p, c_int64, c_void_p]),
         "inrf_adam": (S, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, POINTER(AdamParams), c_void_p,
                           c_void_p]),
+        "inrf_render_nolf": (S, [POINTER(ModelDesc), POINTER(CubesDesc), c_int32, POINTER(CameraDesc), c_void_p,
+                                 c_void_p, c_void_p, c_void_p, c_int64, c_void_p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -73,33 +73,41 @@ struct Mfma<__bf16> {
 __host__ __device__ constexpr int feature_slots(int lmax, int V) {
     return V == 1 ? ((2 * lmax + 15) / 16) * 16 : ((2 * lmax + 31) / 32) * 32;
 }
-// Number of first-layer instructions per output tile.
-__host__ __device__ constexpr int l1_steps(int F, int V) { return V == 1 ? F / 4 + 4 : F / 32 + 1; }
+// Number of first-layer instructions per output tile; X extra inputs (0 or
+// 1) follow the SH values: FP32 takes one more step for them, FP16/BF16
+// have room in the SH step.
+__host__ __device__ constexpr int l1_steps(int F, int V, int X = 0) {
+    return V == 1 ? F / 4 + 4 + X : F / 32 + 1;
+}
 // Steps of layers 2 and 3 (K = 64).
 __host__ __device__ constexpr int hid_steps(int V) { return V == 1 ? 16 : 2; }
 // LDS image, in units of one lane's operand (P::vec), 64 lanes per fragment:
 //   W1 fragments (mt, s), W2 fragments (ot, s), W3 fragments (s).
-__host__ __device__ constexpr int weight_vecs(int F, int V) {
-    return 64 * (4 * l1_steps(F, V) + 4 * hid_steps(V) + hid_steps(V));
+__host__ __device__ constexpr int weight_vecs(int F, int V, int X = 0) {
+    return 64 * (4 * l1_steps(F, V, X) + 4 * hid_steps(V) + hid_steps(V));
 }
-__host__ __device__ constexpr int weight_bytes(int F, int V) { return weight_vecs(F, V) * (V == 1 ? 4 : 16); }
+__host__ __device__ constexpr int weight_bytes(int F, int V, int X = 0) {
+    return weight_vecs(F, V, X) * (V == 1 ? 4 : 16);
+}
 
 // Natural input index carried by element i of lane group g at first-layer
-// step s, or -1 for padding (n_levels real levels, F feature slots).
-__device__ __forceinline__ int l1_index(int V, int F, int n_levels, int s, int g, int i) {
+// step s, or -1 for padding (n_levels real levels, F feature slots, X extra
+// inputs after the SH values).
+__device__ __forceinline__ int l1_index(int V, int F, int n_levels, int s, int g, int i, int X = 0) {
     if (V == 1) {
         if (s < F / 4) {
             const int slot = 16 * (s / 4) + 4 * g + (s % 4);
             return slot < 2 * n_levels ? slot : -1;
         }
-        return 2 * n_levels + 4 * g + (s - F / 4);
+        if (s < F / 4 + 4) return 2 * n_levels + 4 * g + (s - F / 4);
+        return g < X ? 2 * n_levels + INRF_SH_DIM + g : -1;
     }
     if (s < F / 32) {
         const int slot = 32 * s + 8 * g + i;
         return slot < 2 * n_levels ? slot : -1;
     }
     const int k = 8 * g + i;
-    return k < INRF_SH_DIM ? 2 * n_levels + k : -1;
+    return k < INRF_SH_DIM + X ? 2 * n_levels + k : -1;
 }
 
 // Hidden unit fed by element i of lane group g at hidden-layer step s.
@@ -108,16 +116,16 @@ __device__ __forceinline__ int hidden_index(int V, int s, int g, int i) {
     return i < 4 ? 32 * s + 4 * g + i : 32 * s + 16 + 4 * g + (i - 4);
 }
 
-template <class P>
+template <class P, int X = 0>
 __device__ inline void stage_weights(const float* __restrict__ w, int n_levels, int F,
                                      typename Mfma<P>::vec* __restrict__ lds) {
     typedef Mfma<P> M;
     constexpr int V = M::V;
-    const int d_in = 2 * n_levels + INRF_SH_DIM;
+    const int d_in = 2 * n_levels + INRF_SH_DIM + X;
     const float* W1 = w;
     const float* W2 = w + kHidden * d_in;
     const float* W3 = W2 + kHidden * kHidden;
-    const int S1 = l1_steps(F, V), SH = hid_steps(V);
+    const int S1 = l1_steps(F, V, X), SH = hid_steps(V);
     const int n1 = 64 * 4 * S1, n2 = 64 * 4 * SH, n3 = 64 * SH;
     for (int e = threadIdx.x; e < n1 + n2 + n3; e += blockDim.x) {
         const int lane = e % 64, g = lane / 16, r = lane % 16;
@@ -125,7 +133,7 @@ __device__ inline void stage_weights(const float* __restrict__ w, int n_levels, 
         if (e < n1) {
             const int f = e / 64, mt = f / S1, s = f % S1;
             for (int i = 0; i < V; ++i) {
-                const int k = l1_index(V, F, n_levels, s, g, i);
+                const int k = l1_index(V, F, n_levels, s, g, i, X);
                 const float x = k >= 0 ? W1[(16 * mt + r) * d_in + k] : 0.f;
                 if constexpr (V == 1) v = M::cvt(x);
                 else v[i] = M::cvt(x);
@@ -151,12 +159,13 @@ __device__ inline void stage_weights(const float* __restrict__ w, int n_levels, 
 
 // The first layer's B operands of this lane: feature slots from row r of the
 // block's LDS tile (element type of the precision for FP16/BF16, FP32
-// otherwise) and the SH values of direction d (ray r of the block).
-template <class P, int F>
+// otherwise), the SH values of direction d (ray r of the block) and, with
+// X = 1, the extra input `extra` of that ray.
+template <class P, int F, int X = 0>
 __device__ __forceinline__ void load_inputs(const void* tile_row, float dx, float dy, float dz,
-                                            typename Mfma<P>::vec* b) {
+                                            typename Mfma<P>::vec* b, float extra = 0.f) {
     typedef Mfma<P> M;
-    constexpr int V = M::V, S1 = l1_steps(F, V);
+    constexpr int V = M::V, S1 = l1_steps(F, V, X);
     const int g = __lane_id() >> 4;
     float sh[16];
     sh16(dx, dy, dz, sh);
@@ -173,6 +182,7 @@ __device__ __forceinline__ void load_inputs(const void* tile_row, float dx, floa
 #pragma unroll
         for (int i = 0; i < 4; ++i)
             b[F / 4 + i] = g == 0 ? sh[i] : (g == 1 ? sh[4 + i] : (g == 2 ? sh[8 + i] : sh[12 + i]));
+        if constexpr (X == 1) b[F / 4 + 4] = g == 0 ? extra : 0.f;
     } else {
         typedef typename M::vec Vec;
         const Vec* row = reinterpret_cast<const Vec*>(tile_row);
@@ -180,7 +190,8 @@ __device__ __forceinline__ void load_inputs(const void* tile_row, float dx, floa
         for (int c = 0; c < F / 32; ++c) b[c] = row[4 * c + g];
         Vec v;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) v[i] = M::cvt(g == 0 ? sh[i] : (g == 1 ? sh[8 + i] : 0.f));
+        for (int i = 0; i < 8; ++i)
+            v[i] = M::cvt(g == 0 ? sh[i] : (g == 1 ? sh[8 + i] : (X == 1 && g == 2 && i == 0 ? extra : 0.f)));
         b[S1 - 1] = v;
     }
 }
@@ -188,12 +199,12 @@ __device__ __forceinline__ void load_inputs(const void* tile_row, float dx, floa
 // The network for this lane's block of 16 rays given its first-layer B
 // operands.  Returns D of the output tile: for lanes l < 16, element i is
 // pre-sigmoid output i of ray l.
-template <class P, int F>
+template <class P, int F, int X = 0>
 __device__ __forceinline__ f32x4 mlp_block(const typename Mfma<P>::vec* __restrict__ W,
                                            const typename Mfma<P>::vec* b1) {
     typedef Mfma<P> M;
     typedef typename M::vec Vec;
-    constexpr int V = M::V, S1 = l1_steps(F, V), SH = hid_steps(V);
+    constexpr int V = M::V, S1 = l1_steps(F, V, X), SH = hid_steps(V);
     const int lane = __lane_id();
     f32x4 h1[4];
 #pragma unroll

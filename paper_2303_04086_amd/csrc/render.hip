@@ -503,16 +503,17 @@ __device__ __forceinline__ void gather_levels(const ModelC& m, float x, float y,
     }
 }
 
-// Geometry of the per-wave LDS tile: 16 rows (rays) of F feature slots.
-template <class P, int LPG>
+// Geometry of the per-wave LDS tile: 16 rows (rays) of F feature slots.  X
+// extra network inputs (0, or 1 for the coarse opacity of the i-NOLF form).
+template <class P, int LPG, int X = 0>
 struct ShadeShape {
     static constexpr int V = Mfma<P>::V;
     static constexpr int LMAX = 4 * LPG;  // levels the instantiation handles
     static constexpr int F = feature_slots(LMAX, V);
     static constexpr int STRIDE = F + (V == 1 ? 4 : 8);  // elements per row, keeps 16-byte alignment
-    static constexpr int S1 = l1_steps(F, V);
+    static constexpr int S1 = l1_steps(F, V, X);
     static constexpr size_t tile_bytes = 16 * STRIDE * sizeof(typename TileElem<P>::type);
-    static constexpr size_t lds_bytes = size_t(weight_bytes(F, V)) + (kThreads / 64) * tile_bytes;
+    static constexpr size_t lds_bytes = size_t(weight_bytes(F, V, X)) + (kThreads / 64) * tile_bytes;
 };
 
 // Persistent waves over the packed hit list, 64 hits per wave step.  Each
@@ -521,18 +522,23 @@ struct ShadeShape {
 // time so their offset loads are in flight together.  The network then runs
 // on four blocks of 16 rays; each block's features pass through the wave's
 // LDS tile into the matrix-core B-operand layout.
-template <class TableT, class P, int LPG>
+// NOLF (the paper's own i-NOLF form): the record's pad holds the ray's
+// coarse opacity, a further network input, and the colour buffer holds the
+// diffuse colour and tint of the hit, which the outputs complete as
+// (c_d + t c_s, alpha).
+template <class TableT, class P, int LPG, bool NOLF = false>
 __global__ __launch_bounds__(kThreads) void k_shade(ModelC m, const HitRec* __restrict__ recs,
                                                     const int32_t* __restrict__ first,
                                                     const int32_t* __restrict__ counter, float* __restrict__ rgba) {
+    constexpr int X = NOLF ? 1 : 0;
     typedef Mfma<P> M;
     typedef typename M::vec Vec;
-    typedef ShadeShape<P, LPG> S;
+    typedef ShadeShape<P, LPG, X> S;
     typedef typename TileElem<P>::type T;
     extern __shared__ float4 lds_v[];
     Vec* W = reinterpret_cast<Vec*>(lds_v);
-    stage_weights<P>(m.weights, m.n_levels, S::F, W);
-    T* tile = reinterpret_cast<T*>(reinterpret_cast<char*>(lds_v) + weight_bytes(S::F, S::V) +
+    stage_weights<P, X>(m.weights, m.n_levels, S::F, W);
+    T* tile = reinterpret_cast<T*>(reinterpret_cast<char*>(lds_v) + weight_bytes(S::F, S::V, X) +
                                    (threadIdx.x / 64) * S::tile_bytes);
     __syncthreads();
     const int lo = first ? *first : 0, n = *counter;  // records [lo, n)
@@ -560,12 +566,21 @@ __global__ __launch_bounds__(kThreads) void k_shade(ModelC m, const HitRec* __re
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             const int src = 16 * b + r;
             Vec b1[S::S1];
-            load_inputs<P, S::F>(tile + r * S::STRIDE, __shfl(h.dx, src), __shfl(h.dy, src), __shfl(h.dz, src), b1);
+            const float extra = NOLF ? __shfl(__int_as_float(h.pad), src) : 0.f;
+            load_inputs<P, S::F, X>(tile + r * S::STRIDE, __shfl(h.dx, src), __shfl(h.dy, src), __shfl(h.dz, src),
+                                    b1, extra);
             const int out = __shfl(h.out, src);
-            const f32x4 o = mlp_block<P, S::F>(W, b1);
-            if (g == 0 && base + src < n)
-                reinterpret_cast<float4*>(rgba)[out] =
-                    make_float4(sigmoidf(o[0]), sigmoidf(o[1]), sigmoidf(o[2]), sigmoidf(o[3]));
+            const f32x4 o = mlp_block<P, S::F, X>(W, b1);
+            if (g == 0 && base + src < n) {
+                float4* px = reinterpret_cast<float4*>(rgba) + out;
+                if constexpr (NOLF) {
+                    const float4 dt = *px;  // diffuse RGB and tint
+                    *px = make_float4(dt.x + dt.w * sigmoidf(o[0]), dt.y + dt.w * sigmoidf(o[1]),
+                                      dt.z + dt.w * sigmoidf(o[2]), sigmoidf(o[3]));
+                } else {
+                    *px = make_float4(sigmoidf(o[0]), sigmoidf(o[1]), sigmoidf(o[2]), sigmoidf(o[3]));
+                }
+            }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();  // the tile is rewritten by the next block
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -665,6 +680,7 @@ __global__ __launch_bounds__(kThreads) void k_mlp(ModelC m, const float* __restr
 
 #include "backward_device.hpp"
 #include "scene_device.hpp"
+#include "nolf_device.hpp"
 
 namespace inrf {
 
@@ -1143,6 +1159,103 @@ void run_scene(const inrf_instance* objects, int32_t n_objs, int32_t precision, 
     }
 }
 
+// ---- the i-NOLF form (k_march)
+
+bool pow2(int32_t v) { return v >= 1 && (v & (v - 1)) == 0; }
+
+CubesC make_cubes(const inrf_cubes* q) {
+    require(q != nullptr, "cubes is NULL");
+    require(pow2(q->base_res) && q->base_res <= 1024, "base_res must be a power of two in [1, 1024]");
+    require(pow2(q->cube_res) && q->cube_res <= 64, "cube_res must be a power of two in [1, 64]");
+    require(q->index && q->density && q->diffuse, "cube index, density and diffuse must be set");
+    require((reinterpret_cast<uintptr_t>(q->diffuse) & 7) == 0 && (reinterpret_cast<uintptr_t>(q->density) & 1) == 0 &&
+                (reinterpret_cast<uintptr_t>(q->index) & 3) == 0,
+            "cube arrays must be aligned (diffuse to 8 bytes)");
+    require(q->n_cubes >= 1, "n_cubes must be >= 1");
+    require(std::isfinite(q->step) && q->step >= 1e-6f && q->step <= 1.f, "step must be in [1e-6, 1]");
+    require(q->t_stop > 0.f && q->t_stop < 1.f, "t_stop must be in (0, 1)");
+    require(std::isfinite(q->w_min) && q->w_min >= 0.f, "w_min must be finite and >= 0");
+    CubesC C;
+    std::memset(&C, 0, sizeof(C));
+    C.index = q->index;
+    C.dens = reinterpret_cast<const __half*>(q->density);
+    C.diff = reinterpret_cast<const __half*>(q->diffuse);
+    C.n_cubes = q->n_cubes;
+    C.b = q->base_res;
+    C.r = q->cube_res;
+    C.r1 = q->cube_res + 1;
+    C.fb = float(q->base_res);
+    C.fr = float(q->cube_res);
+    C.step = q->step;
+    C.t_stop = q->t_stop;
+    C.w_min = q->w_min;
+    C.j_max = int32_t(std::ceil(1.7320509 / double(q->step))) + 2;  // the cube's diagonal holds fewer samples
+    return C;
+}
+
+template <class TableT, class P, int LPG>
+void launch_shade_nolf_t(const ModelC& c, const HitRec* recs, const int32_t* counter, float* rgba, hipStream_t s) {
+    const size_t lds = ShadeShape<P, LPG, 1>::lds_bytes;
+    auto kern = k_shade<TableT, P, LPG, true>;
+    allow_lds(kern, lds);
+    hipLaunchKernelGGL(kern, dim3(resident_grid(kern, lds)), dim3(kThreads), lds, s, c, recs, nullptr, counter, rgba);
+}
+
+template <class TableT>
+void launch_shade_nolf(const ModelC& c, int32_t precision, const HitRec* recs, const int32_t* counter, float* rgba,
+                       hipStream_t s) {
+#define INRF_SHADE_NOLF(LPG)                                                                                 \
+    do {                                                                                                    \
+        if (precision == INRF_PREC_FP32) launch_shade_nolf_t<TableT, float, LPG>(c, recs, counter, rgba, s); \
+        else if (precision == INRF_PREC_FP16)                                                               \
+            launch_shade_nolf_t<TableT, _Float16, LPG>(c, recs, counter, rgba, s);                          \
+        else launch_shade_nolf_t<TableT, __bf16, LPG>(c, recs, counter, rgba, s);                           \
+    } while (0)
+    switch ((c.n_levels + 3) / 4) {
+        case 1: INRF_SHADE_NOLF(1); break;
+        case 2: INRF_SHADE_NOLF(2); break;
+        default: fail(INRF_E_UNSUPPORTED, "the i-NOLF form supports at most 8 levels");
+    }
+#undef INRF_SHADE_NOLF
+}
+
+void run_nolf(const inrf_model* m, const inrf_cubes* cubes, int32_t precision, const inrf_camera* camera, float* rgba,
+              float* depth, float* alpha_c, void* ws, int64_t ws_bytes, void* stream) {
+    check_precision(precision);
+    const ModelC c = make_model(m, true, false);
+    require(m->weights != nullptr, "weights must be set");
+    if (c.n_levels > 8) fail(INRF_E_UNSUPPORTED, "the i-NOLF form supports at most 8 levels");
+    const CubesC C = make_cubes(cubes);
+    const CamC cam = make_camera(camera);
+    const int64_t n = int64_t(cam.W) * cam.H;
+    require(rgba != nullptr && ws != nullptr, "rgba and workspace must be set");
+    require((reinterpret_cast<uintptr_t>(ws) & 255) == 0 && (reinterpret_cast<uintptr_t>(rgba) & 15) == 0,
+            "workspace must be 256-byte and rgba 16-byte aligned");
+    const WsLayout L(n);
+    if (ws_bytes < L.end)
+        fail(INRF_E_SIZE, "workspace of " + std::to_string(ws_bytes) + " bytes < " + std::to_string(L.end) + " needed");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int32_t* counter = ws_at<int32_t>(ws, 0);
+    HitRec* recs = ws_at<HitRec>(ws, L.recs);
+    int2* blk = ws_at<int2>(ws, L.blk);
+    int32_t* offsets = ws_at<int32_t>(ws, L.offsets);
+    int32_t* runs = ws_at<int32_t>(ws, L.runs);
+    const int n_blk = cam.tiles_x * ((cam.H + kTile - 1) / kTile);
+    const MarchArgs a{rgba, depth, alpha_c, ws_at<HitRec>(ws, L.tmp), blk};
+    hipLaunchKernelGGL(k_march, dim3(n_blk), dim3(kThreads), 0, s, C, cam, a);
+    launch_check("k_march");
+    const int n_runs = (n_blk + kScanRun - 1) / kScanRun;
+    hipLaunchKernelGGL(k_scan_local, dim3(n_runs), dim3(kScanThreads), 0, s, blk, n_blk, offsets, runs);
+    launch_check("k_scan_local");
+    hipLaunchKernelGGL(k_scan_runs, dim3(1), dim3(kScanThreads), 0, s, runs, n_runs, counter);
+    launch_check("k_scan_runs");
+    hipLaunchKernelGGL(k_compact, dim3(n_blk), dim3(kThreads), 0, s, blk, offsets, runs, a.tmp, recs);
+    launch_check("k_compact");
+    if (c.table_dtype == INRF_F32) launch_shade_nolf<float>(c, precision, recs, counter, rgba, s);
+    else launch_shade_nolf<__half>(c, precision, recs, counter, rgba, s);
+    launch_check("k_shade");
+}
+
 }  // namespace
 }  // namespace inrf
 
@@ -1153,6 +1266,12 @@ extern "C" {
 int64_t inrf_workspace_size(int64_t n_rays) {
     if (n_rays < 0) return -1;
     return WsLayout(n_rays).end;
+}
+
+inrf_status inrf_render_nolf(const inrf_model* m, const inrf_cubes* cubes, int32_t precision, const inrf_camera* cam,
+                             float* rgba, float* depth, float* alpha_c, void* ws, int64_t ws_bytes, void* stream) {
+    return guarded("inrf_render_nolf",
+                   [&] { run_nolf(m, cubes, precision, cam, rgba, depth, alpha_c, ws, ws_bytes, stream); });
 }
 
 inrf_status inrf_render(const inrf_model* m, int32_t precision, const inrf_camera* cam, float* rgba, float* depth,

@@ -359,6 +359,105 @@ class Renderer:
                                       self._stream(stream)))
 
 
+class NolfRenderer:
+    """A device-resident object in the paper's own i-NOLF form (Sec. 4.2):
+    density and diffuse texture cubes (FP16) over one base-cell index, PSH
+    level tables built from the given key sets, and FP32 network weights
+    whose first layer also takes the coarse opacity (d_in = 2L + 17)."""
+
+    def __init__(self, base_res: int, cube_res: int, index, density, diffuse, res: Sequence[int], level_keys,
+                 weights: Sequence[np.ndarray], features: Callable[[int, PshLevel], np.ndarray], step: float,
+                 t_stop: float = 1e-4, w_min: float = 1e-4, tables=("f32",), device="cuda", psh_seed: int = 1):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the render path runs only on the device")
+        self.torch = torch
+        self.device = torch.device(device)
+        self.res = [int(r) for r in res]
+        self.n_levels = len(self.res)
+        levels = [build_psh_keys(N, level_keys(l), seed=psh_seed) for l, N in enumerate(self.res)]
+        d_in = 2 * self.n_levels + L.SH_DIM + 1
+        w = [np.asarray(x, np.float32) for x in weights]
+        if [x.shape for x in w] != [(L.HIDDEN, d_in), (L.HIDDEN, L.HIDDEN), (L.OUT, L.HIDDEN)]:
+            raise ValueError(f"weights must be shaped [64,{d_in}], [64,64], [4,64]")
+        self.weights = torch.from_numpy(np.concatenate([x.reshape(-1) for x in w])).to(self.device)
+        phi_off, slot_off = 0, 0
+        self.level_desc = []
+        for lv in levels:
+            self.level_desc.append((lv.res, lv.mbar, lv.rbar, phi_off, slot_off))
+            phi_off += brick_entries(lv.rbar)
+            slot_off += brick_entries(lv.mbar)
+        phi = np.zeros(phi_off, np.uint32)
+        host = np.zeros((slot_off, L.FEATURES), np.float32)
+        for l, lv in enumerate(levels):
+            po, so = self.level_desc[l][3], self.level_desc[l][4]
+            phi[po + brick_index(lv.rbar, np.arange(len(lv.phi), dtype=np.int64))] = lv.phi
+            host[so + brick_index(lv.mbar, lv.slots.astype(np.int64))] = np.asarray(features(l, lv), np.float32)
+        self.n_keys = sum(len(lv.keys) for lv in levels)
+        del levels
+        self.phi = torch.from_numpy(phi.view(np.int32)).to(self.device)
+        t32 = torch.from_numpy(host)
+        self.tables = {}
+        for name in tables:
+            self.tables[name] = t32.to(self.device) if name == "f32" else t32.to(torch.float16).to(self.device)
+        del host, t32
+        r1 = int(cube_res) + 1
+        dens = np.asarray(density, np.float32).reshape(-1, r1 ** 3)
+        diff = np.asarray(diffuse, np.float32).reshape(-1, r1 ** 3, 4)
+        if len(dens) != len(diff) or len(dens) < 1:
+            raise ValueError("density and diffuse cubes must have the same, non-zero count")
+        self.index = torch.from_numpy(np.ascontiguousarray(np.asarray(index, np.int32))).to(self.device)
+        self.density = torch.from_numpy(dens).to(torch.float16).to(self.device)
+        self.diffuse = torch.from_numpy(diff).to(torch.float16).to(self.device)
+        self.cubes = L.CubesDesc(int(base_res), int(cube_res), self.index.data_ptr(), self.density.data_ptr(),
+                                 self.diffuse.data_ptr(), len(dens), float(step), float(t_stop), float(w_min), 0)
+        self._ws = None
+        self._descs = {}
+
+    @classmethod
+    def from_workload(cls, w, tables=("f32", "f16"), kind: str = "normal", sigma: float = 1e-2):
+        import synth
+        feats = lambda l, lv: synth.feature_values(w.feature_seed, l, lv.keys, F=w.F, kind=kind, sigma=sigma)
+        return cls(w.b, w.r, w.index, w.density, w.diffuse, w.res, w.level_keys, w.weights, feats, w.step,
+                   tables=tables, psh_seed=w.psh_seed)
+
+    def desc(self, table: str = "f32") -> L.ModelDesc:
+        if table not in self._descs:
+            m = L.ModelDesc()
+            m.n_levels = self.n_levels
+            m.table_dtype = TABLES[table]
+            for l, (res, mbar, rbar, po, so) in enumerate(self.level_desc):
+                m.levels[l].res, m.levels[l].mbar, m.levels[l].rbar = res, mbar, rbar
+                m.levels[l].phi_offset, m.levels[l].slot_offset = po, so
+            m.phi = self.phi.data_ptr()
+            m.table = self.tables[table].data_ptr()
+            m.weights = self.weights.data_ptr()
+            self._descs[table] = m
+        return self._descs[table]
+
+    def workspace(self, n_rays: int):
+        need = int(L.lib().inrf_workspace_size(n_rays))
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = self.torch.empty(need, dtype=self.torch.uint8, device=self.device)
+        return self._ws
+
+    def hit_count(self) -> int:
+        return int(self._ws[:4].view(self.torch.int32).item())
+
+    def render(self, cam, precision="fp32", table="f32", rgba=None, depth=None, alpha_c=None, stream=None):
+        torch = self.torch
+        n = int(cam.width) * int(cam.height)
+        if rgba is None:
+            rgba = torch.empty((int(cam.height), int(cam.width), 4), dtype=torch.float32, device=self.device)
+        ws = self.workspace(n)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        c = _camera_desc(cam)
+        L.check(L.lib().inrf_render_nolf(ctypes.byref(self.desc(table)), ctypes.byref(self.cubes), PRECISIONS[precision],
+                                         ctypes.byref(c), L.ptr(rgba), L.ptr(depth), L.ptr(alpha_c), L.ptr(ws),
+                                         ws.numel(), ctypes.c_void_p(s.cuda_stream)))
+        return rgba
+
+
 class FramePipeline:
     """Frames in flight on `depth` streams of default priority, each with a
     workspace of its own.  A frame's trace (ALU-bound) then overlaps the
