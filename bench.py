@@ -284,6 +284,38 @@ def single_level_bench(torch, P, frames, W, H, multi_ms):
     return out
 
 
+def nolf_bench(torch, P, frames, W, H):
+    """The paper's own i-NOLF form at W x H: density-cube march (b=64, r=8,
+    the instant-NGP step), four PSH levels up to 512, the network with the
+    coarse-opacity input, diffuse + tint composition; FP16 and FP32."""
+    import synth
+    t0 = time.time()
+    w = synth.nolf_object(W, H)
+    R = P.NolfRenderer.from_workload(w, tables=("f32", "f16"))
+    out = {"workload": w.name, "cubes": int(len(w.density)), "levels": w.res, "keys": int(R.n_keys),
+           "step": round(w.step, 7), "setup_s": round(time.time() - t0, 1)}
+    rgba = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
+    for prec, table in (("fp16", "f16"), ("fp32", "f32")):
+        hits = []
+        for c in w.cameras:
+            R.render(c, prec, table, rgba=rgba)
+            torch.cuda.synchronize()
+            hits.append(R.hit_count())
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(frames)]
+        for i in range(frames):
+            ev[i][0].record()
+            R.render(w.cameras[i % len(w.cameras)], prec, table, rgba=rgba)
+            ev[i][1].record()
+        torch.cuda.synchronize()
+        ms = [a.elapsed_time(b) for a, b in ev]
+        out[prec] = {"Mrays_per_s": round(frames * W * H / (sum(ms) / 1e3) / 1e6, 1),
+                     "ms_per_frame": round(sum(ms) / frames, 4), "p99_ms": round(pct(ms, 99), 4),
+                     "hit_fraction": round(sum(hits) / len(hits) / (W * H), 4)}
+        log(f"nolf {prec}: {out[prec]}")
+    del R
+    return out
+
+
 def pipelined_bench(torch, P, R, cams, steps, warmup):
     """Frames of the headline workload with two in flight on two streams
     (FramePipeline): the trace of one frame overlaps the shading of the one
@@ -349,6 +381,8 @@ def main():
     ap.add_argument("--scene-frames", type=int, default=16, help="timed frames of the 12-object scene (0: none)")
     ap.add_argument("--serve-seconds", type=float, default=0.25,
                     help="simulated client time of the serving leg (0: none)")
+    ap.add_argument("--nolf-frames", type=int, default=16,
+                    help="timed frames of the paper's own i-NOLF form (0: none)")
     ap.add_argument("--pipelined-frames", type=int, default=100,
                     help="frames of the two-in-flight throughput leg (0: none)")
     ap.add_argument("--single-frames", type=int, default=16,
@@ -412,6 +446,7 @@ def main():
     serve = serve_bench(torch, P, R, args.serve_seconds) if args.serve_seconds > 0 else None
     piped = (pipelined_bench(torch, P, R, w.cameras, args.pipelined_frames, args.warmup)
              if args.pipelined_frames > 0 else None)
+    nolf = nolf_bench(torch, P, args.nolf_frames, W, H) if args.nolf_frames > 0 else None
     single = (single_level_bench(torch, P, args.single_frames, W, H, out["fp16"][1]["shade_ms_avg"])
               if args.single_frames > 0 else None)
     train = None
@@ -463,6 +498,7 @@ def main():
         "single_level": single,
         "serve": serve,
         "pipelined": piped,
+        "nolf": nolf,
         "train": train,
         "cpu_baseline": base,
         "source": source_hash(),

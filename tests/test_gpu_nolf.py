@@ -5,15 +5,24 @@ tint composition) against the FP64 oracle, through the C ABI.
 Rays the oracle flags ambiguous (near-equal largest weights, transmittance
 near the cut-off, largest weight near w_min, sample range ending on a step)
 may take either answer.  On the others the hit decision and the hit sample
-(depth within a quarter step) must agree exactly.  Tolerances, from the
-arithmetic: the FP32 sample position carries ~2.4e-7 absolute rounding
-(coordinates up to 2.5), which the density slope (sigma_max / shell =
-1024 per unit here) turns into ~2.5e-4 absolute density error and, times the
-step, ~2e-6 in a sample's alpha; summed over the ~10-20 samples in the shell
-alpha_c may move by ~3e-5 at worst, which the network's alpha_c column
-(Xavier, |w| < 0.3) and two hidden layers carry into the colour at a few
-1e-6.  So alpha_c to 1e-4 and FP32 colour to 1e-5 (as for the proxy path);
-FP16 tables and FP16 matrix cores to 2e-3 as elsewhere."""
+(depth within a quarter step) must agree exactly.
+
+Tolerances, from the arithmetic (`fp32_bound`): an FP32 sample position
+carries up to ~3e-7 absolute rounding (coordinates up to 2.5 from a camera
+at distance 2), which the density slope sigma_max / shell turns into a
+density error and, times the step, into an error of each sample's alpha;
+over the <= 20 samples a ray spends in the shell before its transmittance
+drops below 1e-4, alpha_c moves by at most 20 * step * slope * 3e-7, and the
+colour by no more (the network's sensitivity to alpha_c is below 1: Xavier
+weights under 0.3 and sigmoid slopes under 1/4).  That bound is 4.2e-5 on
+the tiny workload (slope 1024, step sqrt(3)/256), whose full frames are
+still held to the proxy path's 1e-5, and 1.7e-4 on the 4K one (slope 16384,
+step sqrt(3)/1024), whose sampled pixels are held to it.  FP16 tables and
+FP16 matrix cores to 2e-3 as elsewhere."""
+
+
+def fp32_bound(w):
+    return max(1e-5, 20 * w.step * (w.sigma_max / w.shell) * 3e-7)
 import numpy as np
 import pytest
 
@@ -107,3 +116,36 @@ def test_nolf_argument_errors(nolf):
     assert call(good, big) == -5
     assert call(good) == 0
     torch.cuda.synchronize()
+
+
+def test_nolf_full_size_sampled():
+    """The 4K i-NOLF workload (b=64, r=8, four levels up to 512, the
+    instant-NGP step) in the launch configuration the benchmark times,
+    checked against the oracle on 1,500 sampled pixels, half of them hits."""
+    import paper_2303_04086_amd as P
+    w = synth.nolf_object(3840, 2160)
+    R = P.NolfRenderer.from_workload(w)
+    m = model_from_workload(w)
+    cam = w.cameras[3]
+    rgba, depth, ac = _render(R, cam)
+    rgba16 = _render(R, cam, "fp16", "f16")[0]
+    rng = np.random.default_rng(17)
+    hits = np.nonzero(np.isfinite(depth))[0]
+    assert len(hits) > 1000
+    pix = np.concatenate([rng.choice(hits, 750, replace=False), rng.choice(len(depth), 750, replace=False)])
+    o, d = oracle.camera_rays(cam, pix // cam.width, pix % cam.width)
+    ora = render_nolf_rays(m, o, d)
+    clear = ~ora["ambiguous"]
+    hit = np.isfinite(depth[pix])
+    assert np.array_equal(hit[clear], ora["hit"][clear])
+    both = hit & ora["hit"]
+    same = both & (np.abs(depth[pix] - np.where(both, ora["t"], 0)) < w.step / 4)
+    assert np.all(same[clear & both])
+    ok = clear & (same | ~hit)
+    e32 = np.abs(rgba[pix] - ora["rgba"])[ok].max()
+    e16 = np.abs(rgba16[pix] - ora["rgba"])[ok].max()
+    eac = np.abs(ac[pix] - ora["alpha_c"])[clear].max()
+    print(f"nolf 4K sampled: ambiguous {int(ora['ambiguous'].sum())}/{len(pix)}, alpha_c {eac:.2e}, "
+          f"fp32 {e32:.2e}, fp16 {e16:.2e}")
+    assert ora["ambiguous"].mean() < 0.05          # half the sample are hits, where the flags fall
+    assert eac <= max(1e-4, fp32_bound(w)) and e32 <= fp32_bound(w) and e16 <= 2e-3
