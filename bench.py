@@ -52,7 +52,15 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def run_frames(torch, R, cams, prec, table, steps, warmup):
+def run_frames(torch, R, cams, prec, table, steps, warmup, split=True):
+    """Timed frames, then the same frames through the stage-event entry
+    point.  The timed pass calls inrf_render, which renders a frame of 8 or
+    more tile rows as two halves on two streams (`split`; otherwise it goes
+    through the stage-event entry point, which never splits); per-frame
+    events on the caller's stream bracket each call.  The stage pass records
+    trace start, shading start and end on the kernels' stream of an unsplit
+    frame: the trace / shade breakdown and the shading launch time of the
+    roofline object come from it."""
     rgba = torch.empty((cams[0].height, cams[0].width, 4), dtype=torch.float32, device="cuda")
     for i in range(warmup):
         R.render(cams[i % len(cams)], prec, table, rgba=rgba)
@@ -63,21 +71,34 @@ def run_frames(torch, R, cams, prec, table, steps, warmup):
         torch.cuda.synchronize()
         hits.append(R.hit_count())
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
-    for trip in ev:                      # create the underlying events before use
+    fr = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
+    for trip in ev + fr:                 # create the underlying events before use
         for e in trip:
             e.record()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
-        R.render(cams[i % len(cams)], prec, table, rgba=rgba, events=ev[i])
+        if split:
+            fr[i][0].record()
+            R.render(cams[i % len(cams)], prec, table, rgba=rgba)
+            fr[i][1].record()
+        else:
+            R.render(cams[i % len(cams)], prec, table, rgba=rgba, events=ev[i])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    frame = [ev[i][0].elapsed_time(ev[i][2]) for i in range(steps)]
+    frame = [fr[i][0].elapsed_time(fr[i][1]) for i in range(steps)] if split else None
+    t1 = time.perf_counter()
+    if split:
+        for i in range(steps):
+            R.render(cams[i % len(cams)], prec, table, rgba=rgba, events=ev[i])
+        torch.cuda.synchronize()
+    stage_wall = time.perf_counter() - t1 if split else wall
+    unsplit = [ev[i][0].elapsed_time(ev[i][2]) for i in range(steps)]
     trace = [ev[i][0].elapsed_time(ev[i][1]) for i in range(steps)]
     shade = [ev[i][1].elapsed_time(ev[i][2]) for i in range(steps)]
     shade_hits = [hits[i % len(cams)] for i in range(steps)]
-    return {"wall_s": wall, "frame_ms": frame, "trace_ms": trace, "shade_ms": shade, "hits": shade_hits,
-            "hits_per_camera": hits}
+    return {"wall_s": wall, "frame_ms": frame or unsplit, "unsplit_ms": unsplit, "stage_wall_s": stage_wall,
+            "trace_ms": trace, "shade_ms": shade, "hits": shade_hits, "hits_per_camera": hits, "split": split}
 
 
 def pct(v, q):
@@ -100,6 +121,9 @@ def summarize(r, W, H, steps, n_levels, table):
         "hit_rays_per_frame_avg": round(sum(r["hits"]) / steps, 1),
         "hit_Mrays_per_s": round(sum(r["hits"]) / r["wall_s"] / 1e6, 2),
         "shade_requested_GBps": round(achieved, 1),
+        "split_frames": r["split"],
+        "unsplit_Mrays_per_s": round(rays / r["stage_wall_s"] / 1e6, 2),
+        "unsplit_p50_ms": round(pct(r["unsplit_ms"], 50), 4),
     }
 
 
@@ -374,6 +398,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mlp", action="store_true")
+    ap.add_argument("--no-split", action="store_true",
+                    help="time unsplit frames only (profiling runs: every shading launch then covers a whole frame)")
     ap.add_argument("--mlp-rays", type=int, default=1 << 24)
     ap.add_argument("--sweep-frames", type=int, default=8, help="frames per sweep case (0: no sweep)")
     ap.add_argument("--train-steps", type=int, default=10, help="timed training steps (0: none)")
@@ -431,11 +457,11 @@ def main():
 
     out = {}
     for prec, table in (("fp16", "f16"), ("fp32", "f32")):
-        r = run_frames(torch, R, w.cameras, prec, table, args.steps, args.warmup)
+        r = run_frames(torch, R, w.cameras, prec, table, args.steps, args.warmup, split=not args.no_split)
         out[prec] = (r, summarize(r, W, H, args.steps, R.n_levels, table))
         log(f"{prec}: {out[prec][1]['value']} Mrays/s, p50 {out[prec][1]['p50_ms']} ms, "
             f"p99 {out[prec][1]['p99_ms']} ms, trace {out[prec][1]['trace_ms_avg']} ms, "
-            f"shade {out[prec][1]['shade_ms_avg']} ms")
+            f"shade {out[prec][1]['shade_ms_avg']} ms; unsplit {out[prec][1]['unsplit_Mrays_per_s']} Mrays/s")
     mlp = {}
     if not args.no_mlp:
         for prec in ("fp16", "fp32"):

@@ -236,7 +236,15 @@ int64_t inrf_workspace_size(int64_t n_rays);
  * row first, not premultiplied), and optionally depth (device float32
  * [height*width], distance along the unit ray, +inf on a miss) and tri
  * (device int32 [height*width], proxy triangle index, -1 on a miss).
- * ws: device workspace of at least inrf_workspace_size(width*height) bytes. */
+ * ws: device workspace of at least inrf_workspace_size(width*height) bytes;
+ * its first two int32 receive the frame's hit-ray count (the sum of both).
+ * A frame of more than 112 pixel rows (8 tile rows of 16) is rendered as
+ * two halves of tile rows: the top on `stream`, the bottom on a second
+ * stream of the library (one per device and caller stream, created on first
+ * use, default priority), forked from and joined back into `stream` with
+ * events, so the trace of one half can run beside the shading of the other.
+ * The pixels are exactly those of an unsplit frame (inrf_render_profiled
+ * and inrf_render_batch never split). */
 inrf_status inrf_render(const inrf_model* m, int32_t precision, const inrf_camera* cam, float* rgba,
                         float* depth, int32_t* tri, void* ws, int64_t ws_bytes, void* stream);
 

@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -442,7 +443,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_local(const int2* __restr
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_runs(int32_t* __restrict__ runs, int n_runs,
-                                                            int32_t* __restrict__ counter) {
+                                                            int32_t* __restrict__ counter,
+                                                            int32_t* __restrict__ clear, int n_clear) {
     __shared__ int s_wave[kScanThreads / 64 + 1];
     int carry = 0;
     for (int r0 = 0; r0 < n_runs; r0 += kScanThreads) {  // n_runs is small: usually one pass
@@ -455,6 +457,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_runs(int32_t* __restrict_
         __syncthreads();
     }
     if (threadIdx.x == 0) *counter = carry;
+    if (int(threadIdx.x) < n_clear) clear[threadIdx.x] = 0;  // the other chunks' counts of an unsplit frame
 }
 
 // Packs the workgroups' records into one list in workgroup order (tile
@@ -690,6 +693,7 @@ namespace {
 using namespace dev;
 
 constexpr int64_t kWsHeader = 256;
+constexpr int kMaxChunks = 2;  // hit counters of a split frame's halves at the start of the header
 
 int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
 
@@ -701,7 +705,7 @@ struct WsLayout {
     int64_t recs, tmp, blk, offsets, runs, end;
     // extra: 2 more tiles per additional camera of a batch
     explicit WsLayout(int64_t n, int64_t extra = 0) {
-        const int64_t nb = n / 8 + 2 + extra, nr = nb / kScanRun + 1;
+        const int64_t nb = n / 8 + 2 + extra, nr = nb / kScanRun + 1 + kMaxChunks;
         recs = kWsHeader;
         tmp = align256(recs + n * int64_t(sizeof(HitRec)));
         blk = align256(tmp + n * int64_t(sizeof(HitRec)));
@@ -912,16 +916,98 @@ void trace_to_hits(const ModelC& c, const CamSet<NCAM>* cams, const float* ray_o
     const int n_runs = (n_blk + kScanRun - 1) / kScanRun;
     hipLaunchKernelGGL(k_scan_local, dim3(n_runs), dim3(kScanThreads), 0, s, blk, n_blk, offsets, runs);
     launch_check("k_scan_local");
-    hipLaunchKernelGGL(k_scan_runs, dim3(1), dim3(kScanThreads), 0, s, runs, n_runs, counter);
+    hipLaunchKernelGGL(k_scan_runs, dim3(1), dim3(kScanThreads), 0, s, runs, n_runs, counter, counter + 1,
+                       kMaxChunks - 1);
     launch_check("k_scan_runs");
     hipLaunchKernelGGL(k_compact, dim3(n_blk), dim3(kThreads), 0, s, blk, offsets, runs, a.tmp, recs);
     launch_check("k_compact");
 }
 
+// The second stream of a split frame: one per (device, caller stream),
+// default priority, non-blocking, created on first use and kept until the
+// process ends.  Frames split from different caller streams then never wait
+// on each other.
+hipStream_t aux_stream(hipStream_t caller) {
+    static std::mutex mu;
+    static std::vector<std::pair<std::pair<int, hipStream_t>, hipStream_t>> streams;
+    int dev = 0;
+    check_hip(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> lock(mu);
+    for (const auto& e : streams)
+        if (e.first.first == dev && e.first.second == caller) return e.second;
+    hipStream_t s2 = nullptr;
+    check_hip(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking), "hipStreamCreate");
+    streams.push_back({{dev, caller}, s2});
+    return s2;
+}
+
+// Trace, pack and shade camera tiles [t0, t1) of one camera on stream s:
+// records of the range go to recs, its hit count to *counter.  The ranges'
+// per-tile entries, scan runs and records occupy disjoint parts of the
+// workspace arrays.
+template <class TableT>
+void camera_range(const ModelC& c, int32_t precision, const CamSet<1>& cams, int t0, int t1, float* rgba,
+                  float* depth, int32_t* tri, HitRec* tmp, int2* blk, int32_t* offsets, int32_t* runs, HitRec* recs,
+                  int32_t* counter, hipStream_t s) {
+    CamSet<1> cs = cams;
+    cs.c[0].tile0 = -t0;  // workgroup b traces tile t0 + b
+    const int n_blk = t1 - t0;
+    const TraceArgs a{nullptr, nullptr, 0, rgba, depth, tri, tmp, blk + t0};
+    hipLaunchKernelGGL((k_trace<true, 1>), dim3(n_blk), dim3(kThreads), 0, s, c, cs, a);
+    launch_check("k_trace");
+    const int n_runs = (n_blk + kScanRun - 1) / kScanRun;
+    hipLaunchKernelGGL(k_scan_local, dim3(n_runs), dim3(kScanThreads), 0, s, blk + t0, n_blk, offsets + t0, runs);
+    launch_check("k_scan_local");
+    hipLaunchKernelGGL(k_scan_runs, dim3(1), dim3(kScanThreads), 0, s, runs, n_runs, counter, nullptr, 0);
+    launch_check("k_scan_runs");
+    hipLaunchKernelGGL(k_compact, dim3(n_blk), dim3(kThreads), 0, s, blk + t0, offsets + t0, runs, tmp, recs);
+    launch_check("k_compact");
+    launch_shade<TableT>(c, precision, recs, nullptr, counter, rgba, s);
+    launch_check("k_shade");
+}
+
+// A camera frame in two halves of tile rows: the top half on the caller's
+// stream, the bottom half on its second stream, forked and joined with
+// events.  Where one half's trace (bound by ALU issue) and the other's
+// shading (bound by HBM gathers) meet, they run side by side.  Every pixel
+// is computed exactly as in the unsplit frame.  Header: hit counts of the
+// two halves at int32 0 and 1.
+template <class TableT>
+void run_split(const ModelC& c, int32_t precision, const CamSet<1>& cams, float* rgba, float* depth, int32_t* tri,
+               void* ws, const WsLayout& L, hipStream_t s) {
+    const CamC& cam = cams.c[0];
+    const int tiles_y = (cam.H + kTile - 1) / kTile, n_tiles = cam.tiles_x * tiles_y;
+    const int tA = (tiles_y / 2) * cam.tiles_x;
+    const int64_t nA = int64_t(tiles_y / 2) * kTile * cam.W;  // pixels of the top half
+    int32_t* counter = ws_at<int32_t>(ws, 0);
+    HitRec* recs = ws_at<HitRec>(ws, L.recs);
+    HitRec* tmp = ws_at<HitRec>(ws, L.tmp);
+    int2* blk = ws_at<int2>(ws, L.blk);
+    int32_t* offsets = ws_at<int32_t>(ws, L.offsets);
+    int32_t* runs = ws_at<int32_t>(ws, L.runs);
+    const int runsA = (tA + kScanRun - 1) / kScanRun;
+    hipStream_t s2 = aux_stream(s);
+    hipEvent_t fork = nullptr, join = nullptr;
+    check_hip(hipEventCreateWithFlags(&fork, hipEventDisableTiming), "hipEventCreate");
+    check_hip(hipEventCreateWithFlags(&join, hipEventDisableTiming), "hipEventCreate");
+    check_hip(hipEventRecord(fork, s), "hipEventRecord");
+    check_hip(hipStreamWaitEvent(s2, fork, 0), "hipStreamWaitEvent");
+    camera_range<TableT>(c, precision, cams, 0, tA, rgba, depth, tri, tmp, blk, offsets, runs, recs, counter, s);
+    camera_range<TableT>(c, precision, cams, tA, n_tiles, rgba, depth, tri, tmp, blk, offsets, runs + runsA,
+                         recs + nA, counter + 1, s2);
+    check_hip(hipEventRecord(join, s2), "hipEventRecord");
+    check_hip(hipStreamWaitEvent(s, join, 0), "hipStreamWaitEvent");
+    check_hip(hipEventDestroy(fork), "hipEventDestroy");
+    check_hip(hipEventDestroy(join), "hipEventDestroy");
+}
+
+// Frames of at least this many tile rows are split in two.
+constexpr int kSplitTileRows = 8;
+
 template <int NCAM>
 void run_path(const inrf_model* m, int32_t precision, const CamSet<NCAM>* cams, const float* ray_o,
               const float* ray_d, int64_t n, float* rgba, float* depth, int32_t* tri, void* ws, int64_t ws_bytes,
-              void* stream, void* const* events = nullptr) {
+              void* stream, void* const* events = nullptr, bool split = false) {
     check_precision(precision);
     const ModelC c = make_model(m, true, true);
     require(m->weights != nullptr, "weights must be set");
@@ -935,6 +1021,13 @@ void run_path(const inrf_model* m, int32_t precision, const CamSet<NCAM>* cams, 
         fail(INRF_E_SIZE, "workspace of " + std::to_string(ws_bytes) + " bytes < " + std::to_string(L.end) +
                               " needed");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if constexpr (NCAM == 1) {
+        if (split && cams && !events && (cams->c[0].H + kTile - 1) / kTile >= kSplitTileRows) {
+            if (c.table_dtype == INRF_F32) run_split<float>(c, precision, *cams, rgba, depth, tri, ws, L, s);
+            else run_split<__half>(c, precision, *cams, rgba, depth, tri, ws, L, s);
+            return;
+        }
+    }
     const int32_t* counter = ws_at<int32_t>(ws, 0);
     const HitRec* recs = ws_at<HitRec>(ws, L.recs);
     record(events, 0, s);
@@ -1145,7 +1238,8 @@ void run_scene(const inrf_instance* objects, int32_t n_objs, int32_t precision, 
     const int n_runs = (n_blk + kScanRun - 1) / kScanRun;
     hipLaunchKernelGGL(k_scan_local, dim3(n_runs), dim3(kScanThreads), 0, s, blk, n_blk, offsets, runs);
     launch_check("k_scan_local");
-    hipLaunchKernelGGL(k_scan_runs, dim3(1), dim3(kScanThreads), 0, s, runs, n_runs, counter);
+    hipLaunchKernelGGL(k_scan_runs, dim3(1), dim3(kScanThreads), 0, s, runs, n_runs, counter, counter + 1,
+                       kMaxChunks - 1);
     launch_check("k_scan_runs");
     hipLaunchKernelGGL(k_compact, dim3(n_blk), dim3(kThreads), 0, s, blk, offsets, runs, a.tmp, recs);
     launch_check("k_compact");
@@ -1247,7 +1341,8 @@ void run_nolf(const inrf_model* m, const inrf_cubes* cubes, int32_t precision, c
     const int n_runs = (n_blk + kScanRun - 1) / kScanRun;
     hipLaunchKernelGGL(k_scan_local, dim3(n_runs), dim3(kScanThreads), 0, s, blk, n_blk, offsets, runs);
     launch_check("k_scan_local");
-    hipLaunchKernelGGL(k_scan_runs, dim3(1), dim3(kScanThreads), 0, s, runs, n_runs, counter);
+    hipLaunchKernelGGL(k_scan_runs, dim3(1), dim3(kScanThreads), 0, s, runs, n_runs, counter, counter + 1,
+                       kMaxChunks - 1);
     launch_check("k_scan_runs");
     hipLaunchKernelGGL(k_compact, dim3(n_blk), dim3(kThreads), 0, s, blk, offsets, runs, a.tmp, recs);
     launch_check("k_compact");
@@ -1279,7 +1374,7 @@ inrf_status inrf_render(const inrf_model* m, int32_t precision, const inrf_camer
     return guarded("inrf_render", [&] {
         const dev::CamSet<1> cs{1, 0, {make_camera(cam)}};
         run_path(m, precision, &cs, nullptr, nullptr, int64_t(cs.c[0].W) * cs.c[0].H, rgba, depth, tri, ws, ws_bytes,
-                 stream);
+                 stream, nullptr, true);
     });
 }
 

@@ -283,8 +283,10 @@ class Renderer:
         return rgba, views
 
     def hit_count(self) -> int:
-        """Hit rays of the last render/forward (reads the workspace counter)."""
-        return int(self._ws[:4].view(self.torch.int32).item())
+        """Hit rays of the last render/forward (reads the workspace header:
+        the hit counts of a frame's two halves, the second zero when the
+        frame was not split)."""
+        return int(self._ws[:8].view(self.torch.int32).sum().item())
 
     def forward(self, o, d, precision="fp32", table="f32", depth=None, tri=None, rgba=None, stream=None):
         torch = self.torch
@@ -442,7 +444,7 @@ class NolfRenderer:
         return self._ws
 
     def hit_count(self) -> int:
-        return int(self._ws[:4].view(self.torch.int32).item())
+        return int(self._ws[:8].view(self.torch.int32).sum().item())
 
     def render(self, cam, precision="fp32", table="f32", rgba=None, depth=None, alpha_c=None, stream=None):
         torch = self.torch
@@ -488,14 +490,16 @@ class FramePipeline:
         self.k += 1
         s = self.streams[slot]
         n = int(cam.width) * int(cam.height)
-        ws = self._workspace(slot, int(L.lib().inrf_workspace_size(n)))
+        ws = self._workspace(slot, int(L.lib().inrf_batch_workspace_size(1, n)))
         if rgba is None:
             rgba = torch.empty((int(cam.height), int(cam.width), 4), dtype=torch.float32, device=self.R.device)
         s.wait_stream(torch.cuda.current_stream(self.R.device))  # outputs allocated / reused by the caller
         for t in (rgba, depth, tri):
             if t is not None:
                 t.record_stream(s)
-        self.R.render(cam, precision, table, rgba=rgba, depth=depth, tri=tri, stream=s, ws=ws)
+        # one-camera batch: frames already overlap each other here, so the
+        # frame is not split in halves as inrf_render would split it
+        self.R.render_batch([cam], precision, table, rgba=rgba.view(-1, 4), depth=depth, tri=tri, stream=s, ws=ws)
         ev = torch.cuda.Event()
         ev.record(s)
         self.events[slot] = ev
