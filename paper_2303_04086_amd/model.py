@@ -232,11 +232,15 @@ class Renderer:
 
     # -- calls -------------------------------------------------------------
     def render(self, cam, precision="fp32", table="f32", rgba=None, depth=None, tri=None, stream=None,
-               events=None, ws=None):
+               events=None, ws=None, split=True):
         """Render one camera.  `events`: optional three recorded
-        torch.cuda.Event objects marking trace start, shading start and end.
-        `ws`: optional uint8 workspace of the caller (frames in flight on
-        different streams need one each); else the renderer's own."""
+        torch.cuda.Event objects marking trace start, shading start and end
+        (the frame is then not split).  `ws`: optional uint8 workspace of the
+        caller (frames in flight on different streams need one each); else
+        the renderer's own.  `split=False`: never render the frame as two
+        halves on two streams (e.g. when frames already overlap)."""
+        if events is None and not split:
+            events = (None, None, None)   # the stage-event entry point never splits
         torch = self.torch
         n = int(cam.width) * int(cam.height)
         if rgba is None:
@@ -490,16 +494,15 @@ class FramePipeline:
         self.k += 1
         s = self.streams[slot]
         n = int(cam.width) * int(cam.height)
-        ws = self._workspace(slot, int(L.lib().inrf_batch_workspace_size(1, n)))
+        ws = self._workspace(slot, int(L.lib().inrf_workspace_size(n)))
         if rgba is None:
             rgba = torch.empty((int(cam.height), int(cam.width), 4), dtype=torch.float32, device=self.R.device)
         s.wait_stream(torch.cuda.current_stream(self.R.device))  # outputs allocated / reused by the caller
         for t in (rgba, depth, tri):
             if t is not None:
                 t.record_stream(s)
-        # one-camera batch: frames already overlap each other here, so the
-        # frame is not split in halves as inrf_render would split it
-        self.R.render_batch([cam], precision, table, rgba=rgba.view(-1, 4), depth=depth, tri=tri, stream=s, ws=ws)
+        # frames already overlap each other here: no split in halves
+        self.R.render(cam, precision, table, rgba=rgba, depth=depth, tri=tri, stream=s, ws=ws, split=False)
         ev = torch.cuda.Event()
         ev.record(s)
         self.events[slot] = ev

@@ -149,3 +149,20 @@ def test_nolf_full_size_sampled():
           f"fp32 {e32:.2e}, fp16 {e16:.2e}")
     assert ora["ambiguous"].mean() < 0.05          # half the sample are hits, where the flags fall
     assert eac <= max(1e-4, fp32_bound(w)) and e32 <= fp32_bound(w) and e16 <= 2e-3
+
+
+@pytest.mark.parametrize("wh", [(3, 5), (17, 9)])
+def test_nolf_small_frames(nolf, wh):
+    """Frames smaller than one tile (ragged in both directions) under a
+    narrow field of view, most rays hitting, agree with the oracle."""
+    w, R, m = nolf
+    cam = synth.look_at_camera(w.cameras[0].origin.astype(np.float64), (0.52, 0.47, 0.5), 12.0, *wh)
+    rgba, depth, ac = _render(R, cam)
+    o, d = oracle.camera_rays(cam)
+    ora = render_nolf_rays(m, o, d)
+    clear = ~ora["ambiguous"]
+    hit = np.isfinite(depth)
+    assert np.array_equal(hit[clear], ora["hit"][clear]) and hit.any()
+    ok = clear & (hit == ora["hit"])
+    assert np.abs(rgba - ora["rgba"])[ok].max() <= 1e-5
+    assert np.abs(ac - ora["alpha_c"])[clear].max() <= 1e-4
