@@ -63,11 +63,11 @@ def run_frames(torch, R, cams, prec, table, steps, warmup, split=True):
     roofline object come from it."""
     rgba = torch.empty((cams[0].height, cams[0].width, 4), dtype=torch.float32, device="cuda")
     for i in range(warmup):
-        R.render(cams[i % len(cams)], prec, table, rgba=rgba)
+        R.render(cams[i % len(cams)], prec, table, rgba=rgba, split=split)
     torch.cuda.synchronize()
     hits = []
     for c in cams:
-        R.render(c, prec, table, rgba=rgba)
+        R.render(c, prec, table, rgba=rgba, split=split)
         torch.cuda.synchronize()
         hits.append(R.hit_count())
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
@@ -467,11 +467,13 @@ def main():
         for prec in ("fp16", "fp32"):
             mlp[prec] = mlp_bench(torch, R, prec, args.mlp_rays)
             log(f"mlp {prec}: {mlp[prec]}")
+    # two frames in flight, measured before the legs that create more streams: with more than four
+    # streams alive the runtime maps several onto one of its four hardware queues
+    piped = (pipelined_bench(torch, P, R, w.cameras, args.pipelined_frames, args.warmup)
+             if args.pipelined_frames > 0 else None)
     sweep = sweep_bench(torch, R, w, args.sweep_frames) if args.sweep_frames > 0 else None
     scene = scene_bench(torch, P, args.scene_frames, W, H) if args.scene_frames > 0 else None
     serve = serve_bench(torch, P, R, args.serve_seconds) if args.serve_seconds > 0 else None
-    piped = (pipelined_bench(torch, P, R, w.cameras, args.pipelined_frames, args.warmup)
-             if args.pipelined_frames > 0 else None)
     nolf = nolf_bench(torch, P, args.nolf_frames, W, H) if args.nolf_frames > 0 else None
     single = (single_level_bench(torch, P, args.single_frames, W, H, out["fp16"][1]["shade_ms_avg"])
               if args.single_frames > 0 else None)
