@@ -37,11 +37,24 @@ struct CubePos {
     float wx, wy, wz;
 };
 
-__device__ __forceinline__ CubePos cube_pos(const CubesC& C, float x, float y, float z) {
+// cell / cell_k (optional): the last cell looked up and its index entry;
+// consecutive samples in one cell then skip the dependent index read.
+__device__ __forceinline__ CubePos cube_pos(const CubesC& C, float x, float y, float z, int32_t* cell = nullptr,
+                                            int32_t* cell_k = nullptr) {
     const float gx = x * C.fb, gy = y * C.fb, gz = z * C.fb;
     const int cx = min(int(gx), C.b - 1), cy = min(int(gy), C.b - 1), cz = min(int(gz), C.b - 1);
     CubePos p;
-    const int32_t k = C.index[(int64_t(cz) * C.b + cy) * C.b + cx];
+    const int32_t lin = (cz * C.b + cy) * C.b + cx;
+    int32_t k;
+    if (cell && *cell == lin) {
+        k = *cell_k;
+    } else {
+        k = C.index[lin];
+        if (cell) {
+            *cell = lin;
+            *cell_k = k;
+        }
+    }
     p.k = k < 0 ? -1 : min<int64_t>(k, C.n_cubes - 1);  // an entry past the table reads its last cube
     const float ux = (gx - float(cx)) * C.fr, uy = (gy - float(cy)) * C.fr, uz = (gz - float(cz)) * C.fr;
     const int px = min(int(ux), C.r - 1), py = min(int(uy), C.r - 1), pz = min(int(uz), C.r - 1);
@@ -141,11 +154,12 @@ __global__ __launch_bounds__(kThreads) void k_march(CubesC C, CamC cam, MarchArg
     float best_w = 0.f, best_t = INFINITY, ac = 0.f, T = 1.f;
     float3 best_x = make_float3(0.f, 0.f, 0.f);
     if (valid && finite && t_in < t_out) {
+        int32_t cell = -1, cell_k = -1;
         for (int j = 0; j < C.j_max;) {
             const float t = t_in + (float(j) + 0.5f) * C.step;
             if (!(t < t_out)) break;
             const float x = clamp01(o.x + t * d.x), y = clamp01(o.y + t * d.y), z = clamp01(o.z + t * d.z);
-            const CubePos p = cube_pos(C, x, y, z);
+            const CubePos p = cube_pos(C, x, y, z, &cell, &cell_k);
             if (p.k < 0) {
                 const float q = (cell_exit(C, o, d, inv, x, y, z) - t_in) / C.step - 0.5f;
                 const float jn = ceilf(q - 0.01f);
