@@ -98,12 +98,14 @@ __device__ __forceinline__ float4 diffuse_at(const CubesC& C, const CubePos& p) 
     return s;
 }
 
-// Exit t of base cell (cx, cy, cz) along the ray (far faces; an axis the
-// ray does not move along never exits).
-__device__ __forceinline__ float cell_exit(const CubesC& C, float3 o, float3 d, float3 inv, float x, float y, float z) {
-    const float gx = x * C.fb, gy = y * C.fb, gz = z * C.fb;
-    const int cx = min(int(gx), C.b - 1), cy = min(int(gy), C.b - 1), cz = min(int(gz), C.b - 1);
-    const float ib = 1.f / C.fb;
+// Exit t along the ray of the cell of a grid of res^3 cells (fres = res)
+// that holds (x, y, z): far faces; an axis the ray does not move along never
+// exits.
+__device__ __forceinline__ float cell_exit(int res, float fres, float3 o, float3 d, float3 inv, float x, float y,
+                                           float z) {
+    const float gx = x * fres, gy = y * fres, gz = z * fres;
+    const int cx = min(int(gx), res - 1), cy = min(int(gy), res - 1), cz = min(int(gz), res - 1);
+    const float ib = 1.f / fres;
     const float ex = d.x > 0.f ? (float(cx + 1) * ib - o.x) * inv.x : (d.x < 0.f ? (float(cx) * ib - o.x) * inv.x : INFINITY);
     const float ey = d.y > 0.f ? (float(cy + 1) * ib - o.y) * inv.y : (d.y < 0.f ? (float(cy) * ib - o.y) * inv.y : INFINITY);
     const float ez = d.z > 0.f ? (float(cz + 1) * ib - o.z) * inv.z : (d.z < 0.f ? (float(cz) * ib - o.z) * inv.z : INFINITY);
@@ -116,7 +118,26 @@ struct MarchArgs {
     float* alpha_c;  // nullable: coarse opacity of every ray (0 outside the cube)
     HitRec* tmp;     // hit records of workgroup b at blk[b].y; pad holds alpha_c's bits
     int2* blk;
+    const uint8_t* macro;  // nullable: occupancy of the (b/kMacro)^3 macro cells
 };
+
+// Macro cells of kMacro^3 base cells: one flag each, set when any of its
+// base cells holds a cube.  An empty macro cell is skipped in one jump.
+constexpr int kMacro = 4;
+
+__global__ void k_cube_macro(const int32_t* __restrict__ index, int b, uint8_t* __restrict__ macro) {
+    const int bm = b / kMacro;
+    const int m = int(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (m >= bm * bm * bm) return;
+    const int mx = m % bm, my = (m / bm) % bm, mz = m / (bm * bm);
+    uint8_t any = 0;
+    for (int k = 0; k < kMacro * kMacro * kMacro; ++k) {
+        const int cx = mx * kMacro + k % kMacro, cy = my * kMacro + (k / kMacro) % kMacro,
+                  cz = mz * kMacro + k / (kMacro * kMacro);
+        any |= index[(int64_t(cz) * b + cy) * b + cx] >= 0 ? 1 : 0;
+    }
+    macro[m] = any;
+}
 
 __global__ __launch_bounds__(kThreads) void k_march(CubesC C, CamC cam, MarchArgs a) {
     __shared__ int s_cnt[kThreads / 64];
@@ -154,14 +175,29 @@ __global__ __launch_bounds__(kThreads) void k_march(CubesC C, CamC cam, MarchArg
     float best_w = 0.f, best_t = INFINITY, ac = 0.f, T = 1.f;
     float3 best_x = make_float3(0.f, 0.f, 0.f);
     if (valid && finite && t_in < t_out) {
-        int32_t cell = -1, cell_k = -1;
+        int32_t cell = -1, cell_k = -1, mcell = -1;
+        const int bm = C.b / kMacro;
+        const float fbm = float(bm);
         for (int j = 0; j < C.j_max;) {
             const float t = t_in + (float(j) + 0.5f) * C.step;
             if (!(t < t_out)) break;
             const float x = clamp01(o.x + t * d.x), y = clamp01(o.y + t * d.y), z = clamp01(o.z + t * d.z);
+            if (a.macro) {
+                const int mx = min(int(x * fbm), bm - 1), my = min(int(y * fbm), bm - 1), mz = min(int(z * fbm), bm - 1);
+                const int m = (mz * bm + my) * bm + mx;
+                if (m != mcell) {  // a macro cell already found occupied is not read again
+                    if (!a.macro[m]) {
+                        const float q = (cell_exit(bm, fbm, o, d, inv, x, y, z) - t_in) / C.step - 0.5f;
+                        const float jn = ceilf(q - 0.01f);
+                        j = jn > float(j + 1) ? (jn < float(C.j_max) ? int(jn) : C.j_max) : j + 1;
+                        continue;
+                    }
+                    mcell = m;
+                }
+            }
             const CubePos p = cube_pos(C, x, y, z, &cell, &cell_k);
             if (p.k < 0) {
-                const float q = (cell_exit(C, o, d, inv, x, y, z) - t_in) / C.step - 0.5f;
+                const float q = (cell_exit(C.b, C.fb, o, d, inv, x, y, z) - t_in) / C.step - 0.5f;
                 const float jn = ceilf(q - 0.01f);
                 j = jn > float(j + 1) ? (jn < float(C.j_max) ? int(jn) : C.j_max) : j + 1;
                 continue;

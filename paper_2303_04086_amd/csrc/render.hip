@@ -1335,7 +1335,17 @@ void run_nolf(const inrf_model* m, const inrf_cubes* cubes, int32_t precision, c
     int32_t* offsets = ws_at<int32_t>(ws, L.offsets);
     int32_t* runs = ws_at<int32_t>(ws, L.runs);
     const int n_blk = cam.tiles_x * ((cam.H + kTile - 1) / kTile);
-    const MarchArgs a{rgba, depth, alpha_c, ws_at<HitRec>(ws, L.tmp), blk};
+    // macro-cell flags go to the record area, unused until k_compact, when
+    // it has room and the base grid divides into macro cells
+    const int bm = C.b / kMacro;
+    uint8_t* macro = nullptr;
+    if (C.b % kMacro == 0 && int64_t(bm) * bm * bm <= n * int64_t(sizeof(HitRec))) {
+        macro = ws_at<uint8_t>(ws, L.recs);
+        hipLaunchKernelGGL(k_cube_macro, dim3(unsigned((bm * bm * bm + 255) / 256)), dim3(256), 0, s, C.index, C.b,
+                           macro);
+        launch_check("k_cube_macro");
+    }
+    const MarchArgs a{rgba, depth, alpha_c, ws_at<HitRec>(ws, L.tmp), blk, macro};
     hipLaunchKernelGGL(k_march, dim3(n_blk), dim3(kThreads), 0, s, C, cam, a);
     launch_check("k_march");
     const int n_runs = (n_blk + kScanRun - 1) / kScanRun;
