@@ -340,6 +340,35 @@ def nolf_bench(torch, P, frames, W, H):
     return out
 
 
+def graph_bench(torch, P, R, frames=200):
+    """One 1920x1080 camera at distance 2, FP16: eager unsplit renders (one
+    library call each) against replays of the same render captured as a
+    HIP graph; wall time over the frames between two synchronisations."""
+    import synth
+    cam = synth.fibonacci_cameras(8, 2.0, 1920, 1080)[0]
+    n = cam.width * cam.height
+    g = P.CapturedFrame(R, cam, "fp16", "f16")
+    out = {"camera": "1920x1080, distance 2", "frames": frames}
+    rgba = torch.empty((cam.height, cam.width, 4), device="cuda")
+    for mode in ("eager", "graph"):
+        for _ in range(5):
+            g.replay() if mode == "graph" else R.render(cam, "fp16", "f16", rgba=rgba, split=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(frames):
+            g.replay() if mode == "graph" else R.render(cam, "fp16", "f16", rgba=rgba, split=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[mode] = {"Mrays_per_s": round(frames * n / dt / 1e6, 1), "ms_per_frame": round(dt / frames * 1e3, 4)}
+    torch.cuda.synchronize()
+    same = bool(torch.equal(g.replay(), R.render(cam, "fp16", "f16", split=False)))
+    torch.cuda.synchronize()
+    out["replay_equals_eager"] = same
+    log(f"graph: {out}")
+    del g
+    return out
+
+
 def pipelined_bench(torch, P, R, cams, steps, warmup):
     """Frames of the headline workload with two in flight on two streams
     (FramePipeline): the trace of one frame overlaps the shading of the one
@@ -407,6 +436,8 @@ def main():
     ap.add_argument("--scene-frames", type=int, default=16, help="timed frames of the 12-object scene (0: none)")
     ap.add_argument("--serve-seconds", type=float, default=0.25,
                     help="simulated client time of the serving leg (0: none)")
+    ap.add_argument("--no-graph", dest="graph", action="store_false",
+                    help="skip the 1080p eager-versus-graph-replay leg")
     ap.add_argument("--nolf-frames", type=int, default=16,
                     help="timed frames of the paper's own i-NOLF form (0: none)")
     ap.add_argument("--pipelined-frames", type=int, default=100,
@@ -471,6 +502,7 @@ def main():
     # streams alive the runtime maps several onto one of its four hardware queues
     piped = (pipelined_bench(torch, P, R, w.cameras, args.pipelined_frames, args.warmup)
              if args.pipelined_frames > 0 else None)
+    graph = graph_bench(torch, P, R) if args.graph else None
     sweep = sweep_bench(torch, R, w, args.sweep_frames) if args.sweep_frames > 0 else None
     scene = scene_bench(torch, P, args.scene_frames, W, H) if args.scene_frames > 0 else None
     serve = serve_bench(torch, P, R, args.serve_seconds) if args.serve_seconds > 0 else None
@@ -526,6 +558,7 @@ def main():
         "single_level": single,
         "serve": serve,
         "pipelined": piped,
+        "graph": graph,
         "nolf": nolf,
         "train": train,
         "cpu_baseline": base,

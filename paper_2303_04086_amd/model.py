@@ -464,6 +464,39 @@ class NolfRenderer:
         return rgba
 
 
+class CapturedFrame:
+    """One camera frame captured as a HIP graph (torch.cuda.CUDAGraph) and
+    replayed: the five launches of an unsplit render of a fixed camera into
+    fixed buffers with a workspace of its own, enqueued with one call.  The
+    path records no memset (counters are written by kernels), so a replay
+    recomputes the frame exactly as the eager render does."""
+
+    def __init__(self, renderer, cam, precision="fp16", table="f16", depth: bool = False, tri: bool = False):
+        torch = renderer.torch
+        self.R, self.torch = renderer, torch
+        n = int(cam.width) * int(cam.height)
+        dev = renderer.device
+        self.rgba = torch.empty((int(cam.height), int(cam.width), 4), dtype=torch.float32, device=dev)
+        self.depth = torch.empty(n, dtype=torch.float32, device=dev) if depth else None
+        self.tri = torch.empty(n, dtype=torch.int32, device=dev) if tri else None
+        self.ws = torch.empty(int(L.lib().inrf_workspace_size(n)), dtype=torch.uint8, device=dev)
+        args = (cam, precision, table)
+        kw = dict(rgba=self.rgba, depth=self.depth, tri=self.tri, ws=self.ws, split=False)
+        side = torch.cuda.Stream(device=dev)
+        side.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(side):   # warm-up: kernel attributes and occupancy queries happen here
+            renderer.render(*args, stream=side, **kw)
+        torch.cuda.current_stream(dev).wait_stream(side)
+        torch.cuda.synchronize(dev)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph, capture_error_mode="relaxed"):
+            renderer.render(*args, stream=torch.cuda.current_stream(dev), **kw)
+
+    def replay(self):
+        self.graph.replay()
+        return self.rgba
+
+
 class FramePipeline:
     """Frames in flight on `depth` streams of default priority, each with a
     workspace of its own.  A frame's trace (ALU-bound) then overlaps the
