@@ -232,7 +232,9 @@ typedef struct inrf_camera {
 /* Workspace bytes needed by inrf_render / inrf_forward for up to n_rays rays. */
 int64_t inrf_workspace_size(int64_t n_rays);
 
-/* Render one camera: rgba (device float32 [height*width][4], row-major, top
+/* Render one camera (the clients of the rendering service send a camera pose
+ * and intrinsics per frame, Sec. 5; every pixel is one ray, Sec. 1): rgba
+ * (device float32 [height*width][4], row-major, top
  * row first, not premultiplied), and optionally depth (device float32
  * [height*width], distance along the unit ray, +inf on a miss) and tri
  * (device int32 [height*width], proxy triangle index, -1 on a miss).
@@ -240,13 +242,23 @@ int64_t inrf_workspace_size(int64_t n_rays);
  * its first two int32 receive the frame's hit-ray count (the sum of both).
  * A frame of more than 112 pixel rows (8 tile rows of 16) is rendered as
  * two halves of tile rows: the top on `stream`, the bottom on a second
- * stream of the library (one per device and caller stream, created on first
- * use, default priority), forked from and joined back into `stream` with
- * events, so the trace of one half can run beside the shading of the other.
- * The pixels are exactly those of an unsplit frame (inrf_render_profiled
- * and inrf_render_batch never split). */
+ * stream owned by the library, forked from and joined back into `stream`
+ * with two events, so the trace of one half can run beside the shading of
+ * the other.  The library creates that stream and its two events on the
+ * first split frame of each (device, caller stream) pair and keeps them
+ * until the process ends (default priority, non-blocking); split frames
+ * issued concurrently from several host threads on one caller stream must
+ * be serialised by the caller.  The pixels are exactly those of an unsplit
+ * frame (inrf_render_profiled and inrf_render_batch never split). */
 inrf_status inrf_render(const inrf_model* m, int32_t precision, const inrf_camera* cam, float* rgba,
                         float* depth, int32_t* tri, void* ws, int64_t ws_bytes, void* stream);
+
+/* The primary rays of a camera (one ray per pixel from the pose a client
+ * sends, Sec. 5) exactly as the render kernels generate them: ray_o
+ * (nullable) and ray_d device float32
+ * [height*width][3], row-major, unit directions.  inrf_forward on these
+ * rays gives every pixel exactly the value inrf_render gives it. */
+inrf_status inrf_camera_rays(const inrf_camera* cam, float* ray_o, float* ray_d, void* stream);
 
 /* inrf_render with stage timing: events (host array of 3 hipEvent_t created
  * by the caller; NULL entries are skipped) are recorded on `stream` before
@@ -311,7 +323,8 @@ typedef struct inrf_instance {
  * -1 on invalid arguments. */
 int64_t inrf_scene_workspace_size(int32_t n_objects, int64_t n_rays);
 
-/* Render one camera over a scene of n_objects (0..INRF_MAX_OBJECTS) objects:
+/* Render one camera over a scene of n_objects (0..INRF_MAX_OBJECTS) objects
+ * (the per-pixel depth composition of objects of Sec. 5, in one pass):
  * per pixel the nearest hit over all objects wins (equal distance: the lower
  * object index), and that object's network shades it from the object-space
  * hit point and direction.  rgba as inrf_render; depth (nullable) is the
@@ -348,11 +361,12 @@ typedef struct inrf_cubes {
     int64_t n_cubes;       /* >= 1 */
     float step;            /* march step in object units, in [1e-6, 1] (e.g. sqrt(3)/1024) */
     float t_stop;          /* the march ends once transmittance falls below this, in (0, 1) (e.g. 1e-4) */
-    float w_min;           /* a ray hits if its largest sample weight is at least this, >= 0 (e.g. 1e-4) */
+    float w_min;           /* a ray hits if its largest sample weight is at least this, in (0, 1] (e.g. 1e-4);
+                              a march that meets no density never hits */
     int32_t pad;
 } inrf_cubes;
 
-/* Render one camera with the i-NOLF form.  The ray (unit direction) is
+/* Render one camera with the i-NOLF form (Sec. 4.2, Eqs. 4-7).  The ray (unit direction) is
  * marched inside [0,1]^3 at t_in + (j + 1/2) step; each sample's density s
  * gives alpha = 1 - exp(-s step), weight w = T alpha and T *= exp(-s step);
  * the march ends after the first sample whose T falls below t_stop.  The
@@ -368,6 +382,18 @@ inrf_status inrf_render_nolf(const inrf_model* m, const inrf_cubes* cubes, int32
                              const inrf_camera* cam, float* rgba, float* depth, float* alpha_c, void* ws,
                              int64_t ws_bytes, void* stream);
 
+/* The shading stage of the i-NOLF form alone (Sec. 4.2, Eqs. 3, 6-7) on n
+ * caller hit points: x device float32 [n][3] (clamped to [0,1]), d device
+ * float32 [n][3] (need not be unit), alpha_c device float32 [n]; rgba
+ * (device float32 [n][4], 16-byte aligned) = (c_d + t c_s, alpha) with c_d
+ * and t read from the diffuse cubes at x (zero in an empty base cell) and
+ * (c_s, alpha) from the network on (encoding of x, SH16 of d, alpha_c),
+ * through the same kernel inrf_render_nolf shades its hits with.  ws:
+ * 256-byte aligned, at least inrf_workspace_size(n) bytes. */
+inrf_status inrf_shade_nolf(const inrf_model* m, const inrf_cubes* cubes, int32_t precision, const float* x,
+                            const float* d, const float* alpha_c, int64_t n, float* rgba, void* ws, int64_t ws_bytes,
+                            void* stream);
+
 /* ------------------------------------------------------------------------
  * Gradient (training, Sec. 4.2 with the loss of Eq. 8).
  * ---------------------------------------------------------------------- */
@@ -377,7 +403,7 @@ inrf_status inrf_render_nolf(const inrf_model* m, const inrf_cubes* cubes, int32
  * per resident workgroup); -1 on invalid arguments. */
 int64_t inrf_backward_workspace_size(const inrf_model* m, int64_t n_rays);
 
-/* Adds the gradient of a loss L with respect to the model's parameters,
+/* Adds the gradient of a loss L (e.g. Eq. 8's, Sec. 4.2) with respect to the model's parameters,
  * given d_rgba = dL/d(rgba) (device float32 [n][4], 16-byte aligned) for the
  * batch of rays ray_o, ray_d (as inrf_forward):
  *   d_table   device float32 [total slots][INRF_FEATURES], the layout of the

@@ -5,7 +5,8 @@ perfect spatial hash and the proxy BVH, and HIP kernels for gfx950.  This
 package is its binding."""
 from ._lib import InrfError, lib, EXPORTED, PREC_FP32, PREC_FP16, PREC_BF16
 from .model import (PshLevel, BvhImage, CapturedFrame, FramePipeline, NolfRenderer, Renderer, Scene, build_bvh, build_psh, build_psh_keys,
-                    psh_params)
+                    camera_rays, psh_params)
 
 __all__ = ["InrfError", "lib", "EXPORTED", "PREC_FP32", "PREC_FP16", "PREC_BF16", "PshLevel", "BvhImage",
-           "CapturedFrame", "FramePipeline", "NolfRenderer", "Renderer", "Scene", "build_bvh", "build_psh", "build_psh_keys", "psh_params"]
+           "CapturedFrame", "FramePipeline", "NolfRenderer", "Renderer", "Scene", "build_bvh", "build_psh", "build_psh_keys", "camera_rays",
+           "psh_params"]

@@ -24,7 +24,7 @@ EXPORTED = [
     "inrf_bvh_copy", "inrf_bvh_free", "inrf_workspace_size", "inrf_render", "inrf_render_profiled",
     "inrf_forward", "inrf_trace",
     "inrf_encode", "inrf_mlp", "inrf_batch_workspace_size", "inrf_render_batch", "inrf_scene_workspace_size", "inrf_render_scene", "inrf_backward_workspace_size",
-    "inrf_backward", "inrf_adam", "inrf_render_nolf",
+    "inrf_backward", "inrf_adam", "inrf_render_nolf", "inrf_shade_nolf", "inrf_camera_rays",
 ]
 
 
@@ -126,6 +126,9 @@ def _declare(lib):
                           c_void_p]),
         "inrf_render_nolf": (S, [POINTER(ModelDesc), POINTER(CubesDesc), c_int32, POINTER(CameraDesc), c_void_p,
                                  c_void_p, c_void_p, c_void_p, c_int64, c_void_p]),
+        "inrf_shade_nolf": (S, [POINTER(ModelDesc), POINTER(CubesDesc), c_int32, c_void_p, c_void_p, c_void_p,
+                                c_int64, c_void_p, c_void_p, c_int64, c_void_p]),
+        "inrf_camera_rays": (S, [POINTER(CameraDesc), c_void_p, c_void_p, c_void_p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

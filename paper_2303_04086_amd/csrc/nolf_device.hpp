@@ -147,12 +147,7 @@ __global__ __launch_bounds__(kThreads) void k_march(CubesC C, CamC cam, MarchArg
     const bool valid = row < cam.H && col < cam.W;
     const int64_t ray = int64_t(row) * cam.W + col;
     const int64_t base = int64_t(ty) * kTile * cam.W + int64_t(tx) * kTile * min(kTile, cam.H - ty * kTile);
-    const float sx = ((2.f * (float(col) + 0.5f)) / float(cam.W) - 1.f) * cam.tan_x;
-    const float sy = (1.f - (2.f * (float(row) + 0.5f)) / float(cam.H)) * cam.tan_y;
-    const float3 v = make_float3(cam.f[0] + sx * cam.r[0] + sy * cam.u[0], cam.f[1] + sx * cam.r[1] + sy * cam.u[1],
-                                 cam.f[2] + sx * cam.r[2] + sy * cam.u[2]);
-    const float il = 1.f / sqrtf(v.x * v.x + v.y * v.y + v.z * v.z);
-    const float3 d = make_float3(v.x * il, v.y * il, v.z * il);
+    const float3 d = camera_dir(cam, row, col);
     const float3 o = make_float3(cam.o[0], cam.o[1], cam.o[2]);
     const float3 inv = make_float3(1.f / d.x, 1.f / d.y, 1.f / d.z);
     // the ray inside [0,1]^3
@@ -216,7 +211,7 @@ __global__ __launch_bounds__(kThreads) void k_march(CubesC C, CamC cam, MarchArg
             ++j;
         }
     }
-    const bool hit = valid && best_w >= C.w_min;
+    const bool hit = valid && best_w > 0.f && best_w >= C.w_min;  // an empty march never hits
     float4 diff = make_float4(0.f, 0.f, 0.f, 0.f);
     if (hit) diff = diffuse_at(C, cube_pos(C, best_x.x, best_x.y, best_x.z));
     if (valid) {
@@ -247,6 +242,25 @@ __global__ __launch_bounds__(kThreads) void k_march(CubesC C, CamC cam, MarchArg
         a.tmp[pos] = h;
     }
     if (threadIdx.x == 0) a.blk[blockIdx.x] = make_int2(total, int(base));
+}
+
+// The shading stage of the i-NOLF form on caller hit points (one thread per
+// point): the diffuse colour and tint at x (zero in an empty base cell) go to
+// rgba, and a hit record (x, unit direction, alpha_c in the pad) to recs in
+// input order, for k_shade<..., NOLF>.  Thread 0 writes the record count.
+__global__ __launch_bounds__(kThreads) void k_nolf_points(CubesC C, const float* __restrict__ x,
+                                                          const float* __restrict__ d, const float* __restrict__ ac,
+                                                          int64_t n, float* __restrict__ rgba,
+                                                          HitRec* __restrict__ recs, int32_t* __restrict__ counter) {
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i == 0) *counter = int32_t(n);
+    if (i >= n) return;
+    const float px = clamp01(x[3 * i]), py = clamp01(x[3 * i + 1]), pz = clamp01(x[3 * i + 2]);
+    const CubePos p = cube_pos(C, px, py, pz);
+    reinterpret_cast<float4*>(rgba)[i] = p.k < 0 ? make_float4(0.f, 0.f, 0.f, 0.f) : diffuse_at(C, p);
+    const float dx = d[3 * i], dy = d[3 * i + 1], dz = d[3 * i + 2];
+    const float inv = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
+    recs[i] = HitRec{px, py, pz, int32_t(i), dx * inv, dy * inv, dz * inv, __float_as_int(ac[i])};
 }
 
 }  // namespace dev

@@ -53,6 +53,20 @@ struct CamC {
     int64_t pix0;        // first output pixel of this camera in a batch
 };
 
+// Unit direction of the ray through the centre of pixel (row, col):
+// normalize(f + s_x r + s_y u) with s_x = (2(col + 1/2)/W - 1) tan_x and
+// s_y = (1 - 2(row + 1/2)/H) tan_y.  Every kernel that generates camera
+// rays (and inrf_camera_rays) calls this one function, so their rays are
+// bit-identical.
+__device__ __forceinline__ float3 camera_dir(const CamC& cam, int row, int col) {
+    const float sx = ((2.f * (float(col) + 0.5f)) / float(cam.W) - 1.f) * cam.tan_x;
+    const float sy = (1.f - (2.f * (float(row) + 0.5f)) / float(cam.H)) * cam.tan_y;
+    const float3 v = make_float3(cam.f[0] + sx * cam.r[0] + sy * cam.u[0], cam.f[1] + sx * cam.r[1] + sy * cam.u[1],
+                                 cam.f[2] + sx * cam.r[2] + sy * cam.u[2]);
+    const float inv = 1.f / sqrtf(v.x * v.x + v.y * v.y + v.z * v.z);
+    return make_float3(v.x * inv, v.y * inv, v.z * inv);
+}
+
 // Cameras traced by one launch: tiles of camera j are [c[j].tile0, c[j+1].tile0).
 constexpr int kMaxCameras = INRF_MAX_CAMERAS;
 template <int NCAM>
@@ -332,12 +346,7 @@ __global__ __launch_bounds__(kThreads) void k_trace(ModelC m, CamSet<NCAM> cams,
         valid = row < cam.H && col < cam.W;
         ray = cam.pix0 + int64_t(row) * cam.W + col;
         base = cam.pix0 + int64_t(ty) * kTile * cam.W + int64_t(tx) * kTile * min(kTile, cam.H - ty * kTile);
-        const float sx = ((2.f * (float(col) + 0.5f)) / float(cam.W) - 1.f) * cam.tan_x;
-        const float sy = (1.f - (2.f * (float(row) + 0.5f)) / float(cam.H)) * cam.tan_y;
-        float3 v = make_float3(cam.f[0] + sx * cam.r[0] + sy * cam.u[0], cam.f[1] + sx * cam.r[1] + sy * cam.u[1],
-                               cam.f[2] + sx * cam.r[2] + sy * cam.u[2]);
-        const float inv = 1.f / sqrtf(v.x * v.x + v.y * v.y + v.z * v.z);
-        d = make_float3(v.x * inv, v.y * inv, v.z * inv);
+        d = camera_dir(cam, row, col);
         o = make_float3(cam.o[0], cam.o[1], cam.o[2]);
     } else {
         ray = int64_t(blockIdx.x) * kThreads + threadIdx.x;
@@ -591,6 +600,26 @@ __global__ __launch_bounds__(kThreads) void k_shade(ModelC m, const HitRec* __re
     }
 }
 
+// ------------------------------------------------------------ camera rays --
+
+// Origin and unit direction of every pixel ray of one camera, row-major
+// (the rays the camera kernels generate, through camera_dir).
+__global__ __launch_bounds__(kThreads) void k_camera_rays(CamC cam, float* __restrict__ ray_o,
+                                                          float* __restrict__ ray_d) {
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= int64_t(cam.W) * cam.H) return;
+    const int row = int(i / cam.W), col = int(i % cam.W);
+    const float3 d = camera_dir(cam, row, col);
+    if (ray_o) {
+        ray_o[3 * i] = cam.o[0];
+        ray_o[3 * i + 1] = cam.o[1];
+        ray_o[3 * i + 2] = cam.o[2];
+    }
+    ray_d[3 * i] = d.x;
+    ray_d[3 * i + 1] = d.y;
+    ray_d[3 * i + 2] = d.z;
+}
+
 // --------------------------------------------------- encoder and network --
 
 template <class TableT>
@@ -695,7 +724,7 @@ using namespace dev;
 constexpr int64_t kWsHeader = 256;
 constexpr int kMaxChunks = 2;  // hit counters of a split frame's halves at the start of the header
 
-int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
+constexpr int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
 
 // Workspace of a trace of up to n rays: counter | records | per-tile
 // records | per-tile (count, base) | per-tile offsets | per-run offsets.  A
@@ -704,7 +733,8 @@ int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
 struct WsLayout {
     int64_t recs, tmp, blk, offsets, runs, end;
     // extra: 2 more tiles per additional camera of a batch
-    explicit WsLayout(int64_t n, int64_t extra = 0) {
+    constexpr explicit WsLayout(int64_t n, int64_t extra = 0)
+        : recs(0), tmp(0), blk(0), offsets(0), runs(0), end(0) {
         const int64_t nb = n / 8 + 2 + extra, nr = nb / kScanRun + 1 + kMaxChunks;
         recs = kWsHeader;
         tmp = align256(recs + n * int64_t(sizeof(HitRec)));
@@ -724,16 +754,10 @@ void check_hip(hipError_t e, const char* what) {
     if (e != hipSuccess) fail(INRF_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-int g_num_cus = 0;
-
-int num_cus() {
-    if (g_num_cus == 0) {
-        int dev = 0, n = 0;
-        check_hip(hipGetDevice(&dev), "hipGetDevice");
-        check_hip(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
-        g_num_cus = n > 0 ? n : 1;
-    }
-    return g_num_cus;
+int num_cus(int dev) {
+    int n = 0;
+    check_hip(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
+    return n > 0 ? n : 1;
 }
 
 ModelC make_model(const inrf_model* m, bool need_table, bool need_bvh) {
@@ -791,22 +815,35 @@ ModelC make_model(const inrf_model* m, bool need_table, bool need_bvh) {
 
 void launch_check(const char* what) { check_hip(hipGetLastError(), what); }
 
-// Kernels whose dynamic LDS may exceed the default 64 KB window.
-template <class K>
-void allow_lds(K kernel, size_t bytes) {
-    if (bytes > 65536)
-        check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)),
-                  "hipFuncSetAttribute");
-}
+// Launch set-up of a persistent kernel, done once per (device, kernel, LDS
+// size) and kept until the process ends: the dynamic-LDS attribute (for
+// more than the default 64 KB window) and the resident workgroup count
+// (occupancy per CU times the CUs), so a frame does no host-side queries.
+struct GridEntry {
+    int dev;
+    const void* kernel;
+    size_t lds;
+    unsigned grid;
+};
 
-// Persistent grid: as many workgroups as the device keeps resident.
 template <class K>
 unsigned resident_grid(K kernel, size_t lds) {
+    static std::mutex mu;
+    static std::vector<GridEntry> cache;
+    int dev = 0;
+    check_hip(hipGetDevice(&dev), "hipGetDevice");
+    const void* k = reinterpret_cast<const void*>(kernel);
+    std::lock_guard<std::mutex> lock(mu);
+    for (const GridEntry& e : cache)
+        if (e.dev == dev && e.kernel == k && e.lds == lds) return e.grid;
+    if (lds > 65536)
+        check_hip(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)), "hipFuncSetAttribute");
     int per_cu = 0;
     check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, lds),
               "hipOccupancyMaxActiveBlocksPerMultiprocessor");
-    return unsigned(std::max(1, per_cu) * num_cus());
+    const unsigned grid = unsigned(std::max(1, per_cu) * num_cus(dev));
+    cache.push_back({dev, k, lds, grid});
+    return grid;
 }
 
 template <class TableT, class P, int LPG>
@@ -814,7 +851,6 @@ void launch_shade_t(const ModelC& c, const HitRec* recs, const int32_t* first, c
                     hipStream_t s) {
     const size_t lds = ShadeShape<P, LPG>::lds_bytes;
     auto kern = k_shade<TableT, P, LPG>;
-    allow_lds(kern, lds);
     hipLaunchKernelGGL(kern, dim3(resident_grid(kern, lds)), dim3(kThreads), lds, s, c, recs, first, counter, rgba);
 }
 
@@ -822,7 +858,6 @@ template <class P, int LPG>
 void launch_mlp_t(const ModelC& c, const float* in, int64_t n, float* rgba, hipStream_t s) {
     const size_t lds = size_t(weight_bytes(ShadeShape<P, LPG>::F, ShadeShape<P, LPG>::V));
     auto kern = k_mlp<P, LPG>;
-    allow_lds(kern, lds);
     const int64_t blocks = (n + kThreads / 4 - 1) / (kThreads / 4);  // 16 rays per wave step
     const unsigned grid = unsigned(std::min<int64_t>(blocks, resident_grid(kern, lds)));
     // rows start 16-byte aligned when the input array does and d_in = 2L + 16 is a multiple of 4
@@ -923,22 +958,31 @@ void trace_to_hits(const ModelC& c, const CamSet<NCAM>* cams, const float* ray_o
     launch_check("k_compact");
 }
 
-// The second stream of a split frame: one per (device, caller stream),
-// default priority, non-blocking, created on first use and kept until the
-// process ends.  Frames split from different caller streams then never wait
-// on each other.
-hipStream_t aux_stream(hipStream_t caller) {
+// The second stream of a split frame with its fork and join events: one set
+// per (device, caller stream), default priority, non-blocking, created on
+// first use and kept until the process ends, so a frame creates no runtime
+// objects.  Frames split from different caller streams never wait on each
+// other; frames split from one caller stream are ordered by that stream.
+struct AuxStream {
+    int dev;
+    hipStream_t caller, s2;
+    hipEvent_t fork, join;
+};
+
+AuxStream aux_stream(hipStream_t caller) {
     static std::mutex mu;
-    static std::vector<std::pair<std::pair<int, hipStream_t>, hipStream_t>> streams;
+    static std::vector<AuxStream> streams;
     int dev = 0;
     check_hip(hipGetDevice(&dev), "hipGetDevice");
     std::lock_guard<std::mutex> lock(mu);
     for (const auto& e : streams)
-        if (e.first.first == dev && e.first.second == caller) return e.second;
-    hipStream_t s2 = nullptr;
-    check_hip(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking), "hipStreamCreate");
-    streams.push_back({{dev, caller}, s2});
-    return s2;
+        if (e.dev == dev && e.caller == caller) return e;
+    AuxStream a{dev, caller, nullptr, nullptr, nullptr};
+    check_hip(hipStreamCreateWithFlags(&a.s2, hipStreamNonBlocking), "hipStreamCreate");
+    check_hip(hipEventCreateWithFlags(&a.fork, hipEventDisableTiming), "hipEventCreate");
+    check_hip(hipEventCreateWithFlags(&a.join, hipEventDisableTiming), "hipEventCreate");
+    streams.push_back(a);
+    return a;
 }
 
 // Trace, pack and shade camera tiles [t0, t1) of one camera on stream s:
@@ -986,19 +1030,15 @@ void run_split(const ModelC& c, int32_t precision, const CamSet<1>& cams, float*
     int32_t* offsets = ws_at<int32_t>(ws, L.offsets);
     int32_t* runs = ws_at<int32_t>(ws, L.runs);
     const int runsA = (tA + kScanRun - 1) / kScanRun;
-    hipStream_t s2 = aux_stream(s);
-    hipEvent_t fork = nullptr, join = nullptr;
-    check_hip(hipEventCreateWithFlags(&fork, hipEventDisableTiming), "hipEventCreate");
-    check_hip(hipEventCreateWithFlags(&join, hipEventDisableTiming), "hipEventCreate");
-    check_hip(hipEventRecord(fork, s), "hipEventRecord");
-    check_hip(hipStreamWaitEvent(s2, fork, 0), "hipStreamWaitEvent");
+    const AuxStream aux = aux_stream(s);
+    hipStream_t s2 = aux.s2;
+    check_hip(hipEventRecord(aux.fork, s), "hipEventRecord");
+    check_hip(hipStreamWaitEvent(s2, aux.fork, 0), "hipStreamWaitEvent");
     camera_range<TableT>(c, precision, cams, 0, tA, rgba, depth, tri, tmp, blk, offsets, runs, recs, counter, s);
     camera_range<TableT>(c, precision, cams, tA, n_tiles, rgba, depth, tri, tmp, blk, offsets, runs + runsA,
                          recs + nA, counter + 1, s2);
-    check_hip(hipEventRecord(join, s2), "hipEventRecord");
-    check_hip(hipStreamWaitEvent(s, join, 0), "hipStreamWaitEvent");
-    check_hip(hipEventDestroy(fork), "hipEventDestroy");
-    check_hip(hipEventDestroy(join), "hipEventDestroy");
+    check_hip(hipEventRecord(aux.join, s2), "hipEventRecord");
+    check_hip(hipStreamWaitEvent(s, aux.join, 0), "hipStreamWaitEvent");
 }
 
 // Frames of at least this many tile rows are split in two.
@@ -1047,7 +1087,6 @@ template <class TableT, int LPG>
 unsigned backward_grid_t() {
     const size_t lds = BackShape<LPG>::lds_bytes;
     auto kern = k_backward<TableT, LPG>;
-    allow_lds(kern, lds);
     return resident_grid(kern, lds);
 }
 
@@ -1268,7 +1307,7 @@ CubesC make_cubes(const inrf_cubes* q) {
     require(q->n_cubes >= 1, "n_cubes must be >= 1");
     require(std::isfinite(q->step) && q->step >= 1e-6f && q->step <= 1.f, "step must be in [1e-6, 1]");
     require(q->t_stop > 0.f && q->t_stop < 1.f, "t_stop must be in (0, 1)");
-    require(std::isfinite(q->w_min) && q->w_min >= 0.f, "w_min must be finite and >= 0");
+    require(std::isfinite(q->w_min) && q->w_min > 0.f && q->w_min <= 1.f, "w_min must be in (0, 1]");
     CubesC C;
     std::memset(&C, 0, sizeof(C));
     C.index = q->index;
@@ -1291,7 +1330,6 @@ template <class TableT, class P, int LPG>
 void launch_shade_nolf_t(const ModelC& c, const HitRec* recs, const int32_t* counter, float* rgba, hipStream_t s) {
     const size_t lds = ShadeShape<P, LPG, 1>::lds_bytes;
     auto kern = k_shade<TableT, P, LPG, true>;
-    allow_lds(kern, lds);
     hipLaunchKernelGGL(kern, dim3(resident_grid(kern, lds)), dim3(kThreads), lds, s, c, recs, nullptr, counter, rgba);
 }
 
@@ -1361,6 +1399,41 @@ void run_nolf(const inrf_model* m, const inrf_cubes* cubes, int32_t precision, c
     launch_check("k_shade");
 }
 
+void run_shade_nolf(const inrf_model* m, const inrf_cubes* cubes, int32_t precision, const float* x, const float* d,
+                    const float* alpha_c, int64_t n, float* rgba, void* ws, int64_t ws_bytes, void* stream) {
+    check_precision(precision);
+    const ModelC c = make_model(m, true, false);
+    require(m->weights != nullptr, "weights must be set");
+    if (c.n_levels > 8) fail(INRF_E_UNSUPPORTED, "the i-NOLF form supports at most 8 levels");
+    const CubesC C = make_cubes(cubes);
+    require(n >= 0 && n <= (int64_t(1) << 31) - 1, "n must be in [0, 2^31 - 1]");
+    if (n == 0) return;
+    require(x && d && alpha_c && rgba && ws, "x, d, alpha_c, rgba and workspace must be set");
+    require((reinterpret_cast<uintptr_t>(ws) & 255) == 0 && (reinterpret_cast<uintptr_t>(rgba) & 15) == 0,
+            "workspace must be 256-byte and rgba 16-byte aligned");
+    const WsLayout L(n);
+    if (ws_bytes < L.end)
+        fail(INRF_E_SIZE, "workspace of " + std::to_string(ws_bytes) + " bytes < " + std::to_string(L.end) + " needed");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int32_t* counter = ws_at<int32_t>(ws, 0);
+    HitRec* recs = ws_at<HitRec>(ws, L.recs);
+    hipLaunchKernelGGL(k_nolf_points, dim3(unsigned((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, C, x, d,
+                       alpha_c, n, rgba, recs, counter);
+    launch_check("k_nolf_points");
+    if (c.table_dtype == INRF_F32) launch_shade_nolf<float>(c, precision, recs, counter, rgba, s);
+    else launch_shade_nolf<__half>(c, precision, recs, counter, rgba, s);
+    launch_check("k_shade");
+}
+
+void run_camera_rays(const inrf_camera* camera, float* ray_o, float* ray_d, void* stream) {
+    const CamC cam = make_camera(camera);
+    require(ray_d != nullptr, "ray_d must be set");
+    const int64_t n = int64_t(cam.W) * cam.H;
+    hipLaunchKernelGGL(k_camera_rays, dim3(unsigned((n + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+                       reinterpret_cast<hipStream_t>(stream), cam, ray_o, ray_d);
+    launch_check("k_camera_rays");
+}
+
 }  // namespace
 }  // namespace inrf
 
@@ -1377,6 +1450,17 @@ inrf_status inrf_render_nolf(const inrf_model* m, const inrf_cubes* cubes, int32
                              float* rgba, float* depth, float* alpha_c, void* ws, int64_t ws_bytes, void* stream) {
     return guarded("inrf_render_nolf",
                    [&] { run_nolf(m, cubes, precision, cam, rgba, depth, alpha_c, ws, ws_bytes, stream); });
+}
+
+inrf_status inrf_shade_nolf(const inrf_model* m, const inrf_cubes* cubes, int32_t precision, const float* x,
+                            const float* d, const float* alpha_c, int64_t n, float* rgba, void* ws, int64_t ws_bytes,
+                            void* stream) {
+    return guarded("inrf_shade_nolf",
+                   [&] { run_shade_nolf(m, cubes, precision, x, d, alpha_c, n, rgba, ws, ws_bytes, stream); });
+}
+
+inrf_status inrf_camera_rays(const inrf_camera* cam, float* ray_o, float* ray_d, void* stream) {
+    return guarded("inrf_camera_rays", [&] { run_camera_rays(cam, ray_o, ray_d, stream); });
 }
 
 inrf_status inrf_render(const inrf_model* m, int32_t precision, const inrf_camera* cam, float* rgba, float* depth,

@@ -60,12 +60,7 @@ __global__ __launch_bounds__(kThreads) void k_trace_scene(SceneC sc, CamC cam, S
     const bool valid = row < cam.H && col < cam.W;
     const int64_t ray = int64_t(row) * cam.W + col;
     const int64_t base = int64_t(ty) * kTile * cam.W + int64_t(tx) * kTile * min(kTile, cam.H - ty * kTile);
-    const float sx = ((2.f * (float(col) + 0.5f)) / float(cam.W) - 1.f) * cam.tan_x;
-    const float sy = (1.f - (2.f * (float(row) + 0.5f)) / float(cam.H)) * cam.tan_y;
-    float3 v = make_float3(cam.f[0] + sx * cam.r[0] + sy * cam.u[0], cam.f[1] + sx * cam.r[1] + sy * cam.u[1],
-                           cam.f[2] + sx * cam.r[2] + sy * cam.u[2]);
-    const float inv = 1.f / sqrtf(v.x * v.x + v.y * v.y + v.z * v.z);
-    const float3 d = make_float3(v.x * inv, v.y * inv, v.z * inv);
+    const float3 d = camera_dir(cam, row, col);
     const float3 o = make_float3(cam.o[0], cam.o[1], cam.o[2]);
     const RayPre Rw = ray_setup(o, d);
 

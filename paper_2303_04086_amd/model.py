@@ -145,6 +145,18 @@ def _camera_desc(cam) -> L.CameraDesc:
     return c
 
 
+def camera_rays(cam, device="cuda", stream=None):
+    """The camera's primary rays as the render kernels generate them
+    (inrf_camera_rays): origins and unit directions, float32 [H*W, 3] each."""
+    import torch
+    n = int(cam.width) * int(cam.height)
+    o = torch.empty((n, 3), dtype=torch.float32, device=device)
+    d = torch.empty((n, 3), dtype=torch.float32, device=device)
+    s = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
+    L.check(L.lib().inrf_camera_rays(ctypes.byref(_camera_desc(cam)), L.ptr(o), L.ptr(d), ctypes.c_void_p(s.cuda_stream)))
+    return o, d
+
+
 class Renderer:
     """A device-resident i-NOLF object: PSH offset tables and feature tables
     (FP32 and/or FP16), FP32 network weights, and the proxy BVH."""
@@ -461,6 +473,22 @@ class NolfRenderer:
         L.check(L.lib().inrf_render_nolf(ctypes.byref(self.desc(table)), ctypes.byref(self.cubes), PRECISIONS[precision],
                                          ctypes.byref(c), L.ptr(rgba), L.ptr(depth), L.ptr(alpha_c), L.ptr(ws),
                                          ws.numel(), ctypes.c_void_p(s.cuda_stream)))
+        return rgba
+
+
+    def shade(self, x, d, alpha_c, precision="fp32", table="f32", rgba=None, stream=None):
+        """The shading stage alone (inrf_shade_nolf) on hit points x [n, 3],
+        directions d [n, 3] and coarse opacities alpha_c [n]."""
+        torch = self.torch
+        x, d, alpha_c = x.contiguous(), d.contiguous(), alpha_c.contiguous()
+        n = x.shape[0]
+        if rgba is None:
+            rgba = torch.empty((n, 4), dtype=torch.float32, device=self.device)
+        ws = self.workspace(n)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        L.check(L.lib().inrf_shade_nolf(ctypes.byref(self.desc(table)), ctypes.byref(self.cubes), PRECISIONS[precision],
+                                        L.ptr(x), L.ptr(d), L.ptr(alpha_c), n, L.ptr(rgba), L.ptr(ws), ws.numel(),
+                                        ctypes.c_void_p(s.cuda_stream)))
         return rgba
 
 

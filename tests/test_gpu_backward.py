@@ -115,6 +115,25 @@ def test_backward_matches_oracle(tiny, R, omodel, opsh):
     assert np.abs(rgba[keep] - ref["rgba"][keep]).max() <= 1e-5
 
 
+@pytest.mark.parametrize("levels", [6, 10, 16])
+def test_backward_more_levels(levels):
+    """The gradient kernel's wider instantiations (5-8, 9-12 and 13-16
+    levels; sixteen is the training configuration's input width of 48, with
+    the whole weight gradient in accumulator registers) against the oracle:
+    levels geometric from 8 to 96 on the tiny proxy, 2,400 rays."""
+    w = synth.workload_tiny()
+    w.res = [int(round(8 * 12.0 ** (l / (levels - 1)))) for l in range(levels)]
+    w.weights = synth.xavier_mlp(3 + levels, w.d_in)
+    Rl = make_renderer(w, tables=("f32",), kind=KIND, sigma=SIGMA)
+    model = oracle.Model.from_workload(w, kind=KIND, sigma=SIGMA)
+    opsh = [oracle.PSHLevel(lv.res, lv.mbar, lv.rbar, lv.phi, None) for lv in Rl.levels]
+    _, _, _, keep, dt, dw, rgba, ref = _case(Rl, model, 2400, 50 + levels)
+    assert keep.sum() > 1000
+    _check_weights(Rl, dw, ref, f"{levels} levels")
+    _check_table(Rl, dt, ref, opsh, f"{levels} levels")
+    assert np.abs(rgba[keep] - ref["rgba"][keep]).max() <= 1e-5
+
+
 def test_backward_half_table(tiny, R, opsh):
     """FP16 table: the oracle reads the same features rounded to FP16."""
     grids = []

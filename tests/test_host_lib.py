@@ -26,6 +26,37 @@ def test_library_exports_every_declared_symbol():
     assert lib.inrf_version() >= 100
 
 
+# Entry points that carry out a step of the paper's method: each one's
+# comment block in the header cites the passage that defines it.
+CITED = ["inrf_build_psh", "inrf_build_bvh", "inrf_render", "inrf_camera_rays", "inrf_forward", "inrf_render_batch",
+         "inrf_encode", "inrf_mlp", "inrf_render_scene", "inrf_render_nolf", "inrf_shade_nolf", "inrf_backward",
+         "inrf_adam"]
+
+
+def _comment_before(hdr: str, name: str) -> str:
+    """All comment text between the end of the previous top-level
+    declaration (a ';' outside comments and braces) and the declaration of
+    `name`, so a block describing a group, or a parameter struct, counts."""
+    code = re.sub(r"/\*.*?\*/", lambda m: " " * len(m.group(0)), hdr, flags=re.S)
+    at = re.search(r"\b" + name + r"\s*\(", code).start()
+    depth, prev = 0, 0
+    for i, ch in enumerate(code[:at]):
+        depth += ch == "{"
+        depth -= ch == "}"
+        if ch == ";" and depth == 0:
+            prev = i
+    return " ".join(re.findall(r"/\*(.*?)\*/", hdr[prev:at], re.S))
+
+
+def test_header_cites_the_paper_for_every_path_call():
+    hdr = open(os.path.join(ROOT, "include", "inrf.h")).read()
+    for name in CITED:
+        text = _comment_before(hdr, name)
+        assert re.search(r"Sec\. \d|Eqs?\. \d|Kingma", text), f"{name}: no citation in {text[:200]!r}"
+    # the render call cites where poses come from (clients send them per frame)
+    assert "Sec. 5" in _comment_before(hdr, "inrf_render")
+
+
 def test_psh_identical_to_oracle_on_tiny_workload(tiny, tiny_keys):
     levels = P.build_psh(tiny.verts, tiny.tris, tiny.res)
     for N, k, lv in zip(tiny.res, tiny_keys, levels):
@@ -134,6 +165,31 @@ def test_argument_errors():
     assert lib.inrf_encode(ctypes.byref(m), None, 0, None, None, None) == L.INRF_E_INVALID
     assert lib.inrf_workspace_size(-1) == -1
     assert lib.inrf_workspace_size(1000) > 1000 * 16
+
+
+def test_nolf_rejects_nonpositive_w_min():
+    """A largest sample weight of 0 must not count as a hit: w_min <= 0 is an
+    invalid argument, refused on the host before anything touches a device
+    (the pointers below are never dereferenced)."""
+    lib = L.lib()
+    m = L.ModelDesc()
+    m.n_levels, m.table_dtype = 1, L.INRF_F32
+    m.levels[0].res, m.levels[0].mbar, m.levels[0].rbar = 16, 17, 5
+    m.phi = m.table = m.weights = 256
+    cam = L.CameraDesc()
+    cam.forward[:] = [0.0, 0.0, 1.0]
+    cam.right[:] = [1.0, 0.0, 0.0]
+    cam.up[:] = [0.0, 1.0, 0.0]
+    cam.tan_half_fov_y, cam.width, cam.height = 0.36, 4, 4
+    for w_min, ok in ((0.0, False), (-1e-4, False), (float("nan"), False), (1e-4, True)):
+        cubes = L.CubesDesc(16, 4, 256, 256, 256, 1, 0.01, 1e-4, w_min, 0)
+        # a valid w_min passes validation and then stops at the undersized workspace
+        st = lib.inrf_render_nolf(ctypes.byref(m), ctypes.byref(cubes), 0, ctypes.byref(cam), 256, None, None, 256,
+                                  16, None)
+        if ok:
+            assert st == L.INRF_E_SIZE, lib.inrf_last_error()
+        else:
+            assert st == L.INRF_E_INVALID and b"w_min" in lib.inrf_last_error()
 
 
 def test_empty_mesh_builds():

@@ -72,6 +72,21 @@ def test_feature_gradient_matches_finite_differences(setup):
     assert worst < 1e-10, worst
 
 
+def test_eq8_loss_hand_value():
+    """Eq. 8's normalisation fixed by hand: L = (1/N) sum_i (|c_i - c_gt|^2 +
+    (alpha_i - alpha_gt)^2), so the squared errors of a ray's four channels
+    add and the sum over rays is divided by the number of rays (not by 4N).
+    Ray 0: 3 x 0.5^2 + 1^2 = 1.75; ray 1: 1^2 = 1; L = 2.75 / 2 = 1.375.
+    dL/dy = 2 (y - y_gt) / N."""
+    rgba = np.array([[0.5, 0.5, 0.5, 1.0], [0.0, 0.0, 0.0, 0.0]])
+    target = np.array([[0.0, 0.0, 0.0, 0.0], [1.0, 0.0, 0.0, 0.0]])
+    assert oracle.mse_loss(rgba, target) == 1.375
+    assert np.array_equal(oracle.mse_grad(rgba, target), np.array([[0.5, 0.5, 0.5, 1.0], [-1.0, 0.0, 0.0, 0.0]]))
+    # a perfect prediction costs nothing; one ray's error is shared by N
+    assert oracle.mse_loss(target, target) == 0.0
+    assert oracle.mse_loss(np.zeros((4, 4)), np.array([[1.0, 0, 0, 0]] + [[0.0] * 4] * 3)) == 0.25
+
+
 def test_sigmoid_slope_at_zero():
     # zero weights: output 0.5 everywhere, dL/dz3 = dL/dy / 4, no gradient below
     w = synth.workload_tiny()
