@@ -268,6 +268,23 @@ inrf_status inrf_render_profiled(const inrf_model* m, int32_t precision, const i
                                  float* depth, int32_t* tri, void* ws, int64_t ws_bytes, void* stream,
                                  void* const* events);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * inrf_render without a workspace argument.  Its scratch memory is a static
+ * device array of the library (about 64 MiB, held by each GPU the library
+ * runs on until the process ends), so frames are limited to
+ * INRF_STATIC_MAX_PIXELS pixels (INRF_E_SIZE beyond, nothing enqueued).
+ * The call allocates nothing and creates no runtime object; the frame is
+ * never split in halves.  Every call on one GPU shares that array: calls
+ * that may overlap on one GPU (different streams without ordering between
+ * them, or several host threads) race and must be serialised by the
+ * caller.  Nothing in the array needs to start at zero: every value a
+ * frame reads was written earlier in the same frame.  Pixels are exactly
+ * those inrf_render gives. */
+#define INRF_STATIC_MAX_PIXELS 1048576
+inrf_status inrf_render_static(const inrf_model* m, int32_t precision, const inrf_camera* cam, float* rgba,
+                               float* depth, int32_t* tri, void* stream);
+
 /* The same path on a batch of rays ("an indiscriminate range of rays with
  * depths", Sec. 1): ray_o, ray_d device float32 [n][3] (d need not be unit;
  * depth is then the ray parameter t); rgba device float32 [n][4]; depth and

@@ -745,6 +745,33 @@ struct WsLayout {
     }
 };
 
+// Scratch memory of inrf_render_static, for callers that cannot allocate: a
+// file-scope device array that each GPU the library runs on holds until the
+// process ends, sized for the workspace of INRF_STATIC_MAX_PIXELS pixels.
+// Host code never passes `scratch` itself (its name is a host-side stand-in,
+// not a device address): static_scratch() looks up the array's address on
+// the current device once and keeps it.
+constexpr int64_t kStaticScratchBytes = WsLayout(INRF_STATIC_MAX_PIXELS).end;
+static_assert(kStaticScratchBytes <= (int64_t(80) << 20), "static scratch stays modest");
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+void check_hip(hipError_t e, const char* what);
+
+void* static_scratch() {
+    static std::mutex mu;
+    static std::vector<std::pair<int, void*>> addr;
+    int dev = 0;
+    check_hip(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> lock(mu);
+    for (const auto& e : addr)
+        if (e.first == dev) return e.second;
+    void* p = nullptr;
+    check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (p == nullptr) fail(INRF_E_DEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    addr.push_back({dev, p});
+    return p;
+}
+
 template <class T>
 T* ws_at(void* ws, int64_t off) {
     return reinterpret_cast<T*>(reinterpret_cast<char*>(ws) + off);
@@ -1469,6 +1496,20 @@ inrf_status inrf_render(const inrf_model* m, int32_t precision, const inrf_camer
         const dev::CamSet<1> cs{1, 0, {make_camera(cam)}};
         run_path(m, precision, &cs, nullptr, nullptr, int64_t(cs.c[0].W) * cs.c[0].H, rgba, depth, tri, ws, ws_bytes,
                  stream, nullptr, true);
+    });
+}
+
+inrf_status inrf_render_static(const inrf_model* m, int32_t precision, const inrf_camera* cam, float* rgba,
+                               float* depth, int32_t* tri, void* stream) {
+    return guarded("inrf_render_static", [&] {
+        const dev::CamSet<1> cs{1, 0, {make_camera(cam)}};
+        const int64_t n = int64_t(cs.c[0].W) * cs.c[0].H;
+        if (n > INRF_STATIC_MAX_PIXELS)
+            fail(INRF_E_SIZE, "inrf_render_static renders at most " + std::to_string(INRF_STATIC_MAX_PIXELS) +
+                                  " pixels, got " + std::to_string(n));
+        // unsplit: a split frame would need the library's second stream
+        run_path(m, precision, &cs, nullptr, nullptr, n, rgba, depth, tri, static_scratch(), kStaticScratchBytes,
+                 stream, nullptr, false);
     });
 }
 
