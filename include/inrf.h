@@ -271,7 +271,7 @@ inrf_status inrf_render_profiled(const inrf_model* m, int32_t precision, const i
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation):
  * inrf_render without a workspace argument.  Its scratch memory is a static
- * device array of the library (about 64 MiB, held by each GPU the library
+ * device array of the library (74.5 MiB, held by each GPU the library
  * runs on until the process ends), so frames are limited to
  * INRF_STATIC_MAX_PIXELS pixels (INRF_E_SIZE beyond, nothing enqueued).
  * The call allocates nothing and creates no runtime object; the frame is

@@ -37,6 +37,8 @@ namespace dev {
 
 constexpr int kTile = 16;      // camera tiles of 16x16 pixels
 constexpr int kThreads = 256;  // 4 waves
+// prefix sums: workgroup size, and counts each k_scan_local workgroup sums
+constexpr int kScanThreads = 1024, kScanRun = 2 * kScanThreads;
 
 struct alignas(16) HitRec {
     float x, y, z;
@@ -127,25 +129,45 @@ __device__ __forceinline__ RayPre ray_setup(float3 o, float3 d) {
     return R;
 }
 
+// Component of v along axis k of the ray's permutation: a run-time axis
+// (AxisR: the ray's own kx, ky, kz) or compile-time axes (AxisC, for a wave
+// whose rays all share one permutation).  Both select the same value, so
+// the test below is bit-identical either way.
+struct AxisR {
+    int kx, ky, kz;
+    __device__ float x(const float3& v) const { return comp(v, kx); }
+    __device__ float y(const float3& v) const { return comp(v, ky); }
+    __device__ float z(const float3& v) const { return comp(v, kz); }
+};
+template <int KX, int KY, int KZ>
+struct AxisC {
+    __device__ static float pick(const float3& v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
+    __device__ float x(const float3& v) const { return pick(v, KX); }
+    __device__ float y(const float3& v) const { return pick(v, KY); }
+    __device__ float z(const float3& v) const { return pick(v, KZ); }
+};
+
 // Watertight ray/triangle test of Woop, Benthin and Wald (JCGT 2013),
 // two-sided.  Returns t > 0 of the hit or +inf.  Products are not fused so
 // that an edge shared by two triangles gets exactly opposite edge values.
-__device__ __forceinline__ float hit_triangle(const RayPre& R, const float3 v0, const float3 v1, const float3 v2) {
+template <class Ax>
+__device__ __forceinline__ float hit_triangle_ax(const RayPre& R, const Ax& ax, const float3 v0, const float3 v1,
+                                                 const float3 v2) {
 #pragma clang fp contract(off)
     const float3 A = make_float3(v0.x - R.o.x, v0.y - R.o.y, v0.z - R.o.z);
     const float3 B = make_float3(v1.x - R.o.x, v1.y - R.o.y, v1.z - R.o.z);
     const float3 C = make_float3(v2.x - R.o.x, v2.y - R.o.y, v2.z - R.o.z);
-    const float Akz = comp(A, R.kz), Bkz = comp(B, R.kz), Ckz = comp(C, R.kz);
-    const float Ax = comp(A, R.kx) - R.Sx * Akz, Ay = comp(A, R.ky) - R.Sy * Akz;
-    const float Bx = comp(B, R.kx) - R.Sx * Bkz, By = comp(B, R.ky) - R.Sy * Bkz;
-    const float Cx = comp(C, R.kx) - R.Sx * Ckz, Cy = comp(C, R.ky) - R.Sy * Ckz;
+    const float Akz = ax.z(A), Bkz = ax.z(B), Ckz = ax.z(C);
+    const float Ax_ = ax.x(A) - R.Sx * Akz, Ay = ax.y(A) - R.Sy * Akz;
+    const float Bx = ax.x(B) - R.Sx * Bkz, By = ax.y(B) - R.Sy * Bkz;
+    const float Cx = ax.x(C) - R.Sx * Ckz, Cy = ax.y(C) - R.Sy * Ckz;
     float U = Cx * By - Cy * Bx;
-    float V = Ax * Cy - Ay * Cx;
-    float W = Bx * Ay - By * Ax;
+    float V = Ax_ * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax_;
     if (U == 0.f || V == 0.f || W == 0.f) {  // rare: redo the edge tests exactly
         U = float(double(Cx) * double(By) - double(Cy) * double(Bx));
-        V = float(double(Ax) * double(Cy) - double(Ay) * double(Cx));
-        W = float(double(Bx) * double(Ay) - double(By) * double(Ax));
+        V = float(double(Ax_) * double(Cy) - double(Ay) * double(Cx));
+        W = float(double(Bx) * double(Ay) - double(By) * double(Ax_));
     }
     // the rest is select-based: no divergent branches inside a packet
     const bool outside = (U < 0.f || V < 0.f || W < 0.f) && (U > 0.f || V > 0.f || W > 0.f);
@@ -155,6 +177,10 @@ __device__ __forceinline__ float hit_triangle(const RayPre& R, const float3 v0, 
     const float T = det < 0.f ? -T0 : T0;
     const bool ok = !outside && det != 0.f && T > 0.f;
     return ok ? T * __builtin_amdgcn_rcpf(fabsf(det)) : INFINITY;
+}
+
+__device__ __forceinline__ float hit_triangle(const RayPre& R, const float3 v0, const float3 v1, const float3 v2) {
+    return hit_triangle_ax(R, AxisR{R.kx, R.ky, R.kz}, v0, v1, v2);
 }
 
 // Slab test of one child box for t in [0, tmax]; conservative so that
@@ -321,14 +347,22 @@ __device__ void closest_hit_packet(const B& m, const RayPre& R, bool active, int
     }
 }
 
+}  // namespace dev
+}  // namespace inrf
+
+#include "bin_device.hpp"
+
+namespace inrf {
+namespace dev {
+
 // One workgroup per 16x16 camera tile (each wave an 8x8 quadrant, so that a
 // packet is compact) or per 256 batch rays.  Writes depth / triangle / zero
 // colour of misses and, if records are requested, the hit records of the
 // workgroup in lane order to tmp[base ..], base = the index of the
 // workgroup's first ray in the output (tiles of a row band are laid out
 // one after another), with blk[b] = (hits, base).
-template <bool CAMERA, int NCAM>
-__global__ __launch_bounds__(kThreads) void k_trace(ModelC m, CamSet<NCAM> cams, TraceArgs a) {
+template <bool CAMERA, int NCAM, bool BINNED = false>
+__global__ __launch_bounds__(kThreads) void k_trace(ModelC m, CamSet<NCAM> cams, TraceArgs a, BinsC bins) {
     extern __shared__ int stack[];  // batch: [m.stack_depth][kThreads] per-lane stacks
     __shared__ int wst[(kThreads / 64) * kBvhMaxStack];
     __shared__ int s_cnt[kThreads / 64];
@@ -336,6 +370,7 @@ __global__ __launch_bounds__(kThreads) void k_trace(ModelC m, CamSet<NCAM> cams,
     int64_t ray, base;
     bool valid;
     float3 o, d;
+    int qx = 0, qy = 0;  // the wave's quadrant (camera)
     if (CAMERA) {
         int j = 0;  // the camera of this tile (wave-uniform)
         for (int k = 1; k < NCAM && k < cams.n; ++k)
@@ -343,6 +378,8 @@ __global__ __launch_bounds__(kThreads) void k_trace(ModelC m, CamSet<NCAM> cams,
         const CamC& cam = cams.c[j];
         const int tile = int(blockIdx.x) - cam.tile0, tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
         const int row = ty * kTile + 8 * (wave >> 1) + (lane >> 3), col = tx * kTile + 8 * (wave & 1) + (lane & 7);
+        qx = 2 * tx + (wave & 1);
+        qy = 2 * ty + (wave >> 1);
         valid = row < cam.H && col < cam.W;
         ray = cam.pix0 + int64_t(row) * cam.W + col;
         base = cam.pix0 + int64_t(ty) * kTile * cam.W + int64_t(tx) * kTile * min(kTile, cam.H - ty * kTile);
@@ -366,7 +403,8 @@ __global__ __launch_bounds__(kThreads) void k_trace(ModelC m, CamSet<NCAM> cams,
     const bool active = valid && finite;
     if (CAMERA) {
         const RayPre R = ray_setup(o, active ? d : make_float3(0.f, 0.f, 1.f));
-        closest_hit_packet(m, R, active, wst + wave * kBvhMaxStack, t, tri);
+        if constexpr (BINNED) closest_hit_binned(m, bins, qx, qy, R, active, wst + wave * kBvhMaxStack, t, tri);
+        else closest_hit_packet(m, R, active, wst + wave * kBvhMaxStack, t, tri);
     } else if (active) {
         const RayPre R = ray_setup(o, d);
         closest_hit(m, R, stack + threadIdx.x, t, tri);
@@ -409,7 +447,6 @@ __global__ __launch_bounds__(kThreads) void k_trace(ModelC m, CamSet<NCAM> cams,
 // scans runs of kScanRun counts (one workgroup each) and writes each run's
 // total; k_scan_runs scans those totals (one workgroup) and writes the grand
 // total to the counter.  k_compact adds the two.
-constexpr int kScanThreads = 1024, kScanRun = 2 * kScanThreads;
 
 // Inclusive sum of v over the lanes of a wave up to this one.
 __device__ __forceinline__ int wave_scan(int v) {
@@ -439,11 +476,15 @@ __device__ __forceinline__ int block_exclusive(int v, int* s_wave, int* total) {
     return s_wave[wave] + inc - v;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_local(const int2* __restrict__ blk, int n_blk,
-                                                             int32_t* __restrict__ offsets, int32_t* __restrict__ runs) {
+// cnt: counts at cnt[i * stride] (stride 2: the .x of per-tile (count, base)
+// pairs), each taken as min(count, clamp).
+__global__ __launch_bounds__(kScanThreads) void k_scan_local(const int32_t* __restrict__ cnt, int stride, int n_blk,
+                                                             int32_t* __restrict__ offsets, int32_t* __restrict__ runs,
+                                                             int clamp) {
     __shared__ int s_wave[kScanThreads / 64 + 1];
     const int i0 = blockIdx.x * kScanRun + 2 * threadIdx.x;
-    const int c0 = i0 < n_blk ? blk[i0].x : 0, c1 = i0 + 1 < n_blk ? blk[i0 + 1].x : 0;
+    const int c0 = i0 < n_blk ? min(cnt[int64_t(i0) * stride], clamp) : 0,
+              c1 = i0 + 1 < n_blk ? min(cnt[int64_t(i0 + 1) * stride], clamp) : 0;
     int total;
     const int ex = block_exclusive(c0 + c1, s_wave, &total);
     if (i0 < n_blk) offsets[i0] = ex;
@@ -731,17 +772,30 @@ constexpr int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
 // camera of W x H = n pixels has at most ceil(W/16) ceil(H/16) <= n/8 + 2
 // tiles.
 struct WsLayout {
-    int64_t recs, tmp, blk, offsets, runs, end;
-    // extra: 2 more tiles per additional camera of a batch
+    int64_t recs, tmp, blk, offsets, runs;
+    int64_t qcnt, qoff, qruns, qtotal, entries;  // screen bins of a camera frame (bin_device.hpp)
+    int64_t n_quads, n_entries, end;
+    // extra: 2 more tiles per additional camera of a batch.  A W x H = n
+    // pixel frame has ceil(W/8) ceil(H/8) <= n/8 + 1 quadrants; the bins
+    // hold up to 2n triangle records (a quadrant whose list does not fit
+    // walks the BVH instead).
     constexpr explicit WsLayout(int64_t n, int64_t extra = 0)
-        : recs(0), tmp(0), blk(0), offsets(0), runs(0), end(0) {
+        : recs(0), tmp(0), blk(0), offsets(0), runs(0), qcnt(0), qoff(0), qruns(0), qtotal(0), entries(0),
+          n_quads(0), n_entries(0), end(0) {
         const int64_t nb = n / 8 + 2 + extra, nr = nb / kScanRun + 1 + kMaxChunks;
         recs = kWsHeader;
         tmp = align256(recs + n * int64_t(sizeof(HitRec)));
         blk = align256(tmp + n * int64_t(sizeof(HitRec)));
         offsets = align256(blk + nb * int64_t(sizeof(int2)));
         runs = align256(offsets + nb * int64_t(sizeof(int32_t)));
-        end = align256(runs + nr * int64_t(sizeof(int32_t)));
+        n_quads = n / 8 + 1;
+        n_entries = 2 * n;
+        qcnt = align256(runs + nr * int64_t(sizeof(int32_t)));
+        qoff = align256(qcnt + n_quads * int64_t(sizeof(int32_t)));
+        qruns = align256(qoff + n_quads * int64_t(sizeof(int32_t)));
+        qtotal = align256(qruns + (n_quads / kScanRun + 2) * int64_t(sizeof(int32_t)));
+        entries = align256(qtotal + (2 + kBinGlobal) * int64_t(sizeof(int32_t)));
+        end = align256(entries + n_entries * int64_t(sizeof(int32_t)));
     }
 };
 
@@ -939,16 +993,88 @@ void record(void* const* events, int i, hipStream_t s) {
     if (events && events[i]) check_hip(hipEventRecord(reinterpret_cast<hipEvent_t>(events[i]), s), "hipEventRecord");
 }
 
+// Screen bins of one camera frame in the workspace (bin_device.hpp).
+// Returns false (the frame then walks the BVH) when the camera basis is too
+// close to singular for the projection to be conservative.
+bool make_bins(const CamC& cam, void* ws, const WsLayout& L, BinsC& b) {
+    std::memset(&b, 0, sizeof(b));
+    const double r[3] = {cam.r[0], cam.r[1], cam.r[2]}, u[3] = {cam.u[0], cam.u[1], cam.u[2]},
+                 f[3] = {cam.f[0], cam.f[1], cam.f[2]};
+    // inverse of the matrix with columns r, u, f: rows (u x f, f x r, r x u) / det
+    const double uf[3] = {u[1] * f[2] - u[2] * f[1], u[2] * f[0] - u[0] * f[2], u[0] * f[1] - u[1] * f[0]};
+    const double fr[3] = {f[1] * r[2] - f[2] * r[1], f[2] * r[0] - f[0] * r[2], f[0] * r[1] - f[1] * r[0]};
+    const double ru[3] = {r[1] * u[2] - r[2] * u[1], r[2] * u[0] - r[0] * u[2], r[0] * u[1] - r[1] * u[0]};
+    const double det = r[0] * uf[0] + r[1] * uf[1] + r[2] * uf[2];
+    const auto norm = [](const double* v) { return std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); };
+    const double scale = norm(r) * norm(u) * norm(f);
+    if (!(std::fabs(det) > 1e-3 * scale) || !std::isfinite(det)) return false;
+    for (int k = 0; k < 3; ++k) {
+        b.a[k] = float(uf[k] / det);
+        b.a[3 + k] = float(fr[k] / det);
+        b.a[6 + k] = float(ru[k] / det);
+        b.o[k] = cam.o[k];
+        if (!std::isfinite(b.a[k]) || !std::isfinite(b.a[3 + k]) || !std::isfinite(b.a[6 + k]) ||
+            !std::isfinite(b.o[k]))
+            return false;
+    }
+    b.sjx = float(double(cam.W) / (2.0 * double(cam.tan_x)));
+    b.sjb = float(0.5 * double(cam.W) - 0.5);
+    b.siy = float(-double(cam.H) / (2.0 * double(cam.tan_y)));
+    b.sib = float(0.5 * double(cam.H) - 0.5);
+    b.W = cam.W;
+    b.H = cam.H;
+    b.QX = (cam.W + kQuad - 1) / kQuad;
+    b.QY = (cam.H + kQuad - 1) / kQuad;
+    if (int64_t(b.QX) * b.QY > L.n_quads) return false;
+    b.cnt = ws_at<int32_t>(ws, L.qcnt);
+    b.off = ws_at<int32_t>(ws, L.qoff);
+    b.runs = ws_at<int32_t>(ws, L.qruns);
+    b.total = ws_at<int32_t>(ws, L.qtotal);
+    b.entries = ws_at<int32_t>(ws, L.entries);
+    b.E = L.n_entries;
+    b.clamp = int32_t(std::min<int64_t>(L.n_entries + 1, ((int64_t(1) << 31) - 1) / (int64_t(b.QX) * b.QY)));
+    return true;
+}
+
+// Sorts the proxy's triangles into the frame's quadrant lists: clear, count,
+// scan, fill.
+void bin_frame(const ModelC& c, const BinsC& b, hipStream_t s) {
+    const int nq = b.QX * b.QY;
+    hipLaunchKernelGGL(k_bin_clear, dim3(unsigned((nq + 255) / 256)), dim3(256), 0, s, b);
+    launch_check("k_bin_clear");
+    if (c.n_tris == 0) return;
+    const unsigned grid = unsigned((c.n_tris + 255) / 256);
+    hipLaunchKernelGGL(k_bin<false>, dim3(grid), dim3(256), 0, s, b, c.tris, c.n_tris);
+    launch_check("k_bin");
+    const int n_runs = (nq + kScanRun - 1) / kScanRun;
+    hipLaunchKernelGGL(k_scan_local, dim3(n_runs), dim3(kScanThreads), 0, s, b.cnt, 1, nq, b.off, b.runs, b.clamp);
+    launch_check("k_scan_local");
+    hipLaunchKernelGGL(k_scan_runs, dim3(1), dim3(kScanThreads), 0, s, b.runs, n_runs, b.total, nullptr, 0);
+    launch_check("k_scan_runs");
+    hipLaunchKernelGGL(k_bin<true>, dim3(grid), dim3(256), 0, s, b, c.tris, c.n_tris);
+    launch_check("k_bin");
+}
+
 // Clears the hit counter, then traces n rays (camera rays when cam is set),
 // writing depth / triangle / zero colour of misses and appending hit records.
 // Launches k_trace, one workgroup per tile (cameras) or 256-ray block
 // (batch); returns the number of workgroups.
 template <int NCAM>
-int launch_trace(const ModelC& c, const CamSet<NCAM>* cams, const TraceArgs& a, int64_t n, hipStream_t s) {
+int launch_trace(const ModelC& c, const CamSet<NCAM>* cams, const TraceArgs& a, int64_t n, hipStream_t s,
+                 const BinsC* bins) {
+    BinsC none_b;
+    std::memset(&none_b, 0, sizeof(none_b));
     if (cams) {
         const CamC& last = cams->c[cams->n - 1];
         const int n_blk = last.tile0 + last.tiles_x * ((last.H + kTile - 1) / kTile);
-        hipLaunchKernelGGL((k_trace<true, NCAM>), dim3(n_blk), dim3(kThreads), 0, s, c, *cams, a);
+        if constexpr (NCAM == 1) {
+            if (bins) {
+                hipLaunchKernelGGL((k_trace<true, 1, true>), dim3(n_blk), dim3(kThreads), 0, s, c, *cams, a, *bins);
+                launch_check("k_trace");
+                return n_blk;
+            }
+        }
+        hipLaunchKernelGGL((k_trace<true, NCAM>), dim3(n_blk), dim3(kThreads), 0, s, c, *cams, a, none_b);
         launch_check("k_trace");
         return n_blk;
     }
@@ -956,7 +1082,7 @@ int launch_trace(const ModelC& c, const CamSet<NCAM>* cams, const TraceArgs& a, 
     std::memset(&none, 0, sizeof(none));
     const int n_blk = int((n + kThreads - 1) / kThreads);
     const size_t stack_bytes = size_t(c.stack_depth) * kThreads * sizeof(int);
-    hipLaunchKernelGGL((k_trace<false, 1>), dim3(n_blk), dim3(kThreads), stack_bytes, s, c, none, a);
+    hipLaunchKernelGGL((k_trace<false, 1>), dim3(n_blk), dim3(kThreads), stack_bytes, s, c, none, a, none_b);
     launch_check("k_trace");
     return n_blk;
 }
@@ -966,7 +1092,7 @@ int launch_trace(const ModelC& c, const CamSet<NCAM>* cams, const TraceArgs& a, 
 // workgroup order and writes its length to the counter.
 template <int NCAM>
 void trace_to_hits(const ModelC& c, const CamSet<NCAM>* cams, const float* ray_o, const float* ray_d, int64_t n,
-                   float* rgba, float* depth, int32_t* tri, void* ws, hipStream_t s) {
+                   float* rgba, float* depth, int32_t* tri, void* ws, hipStream_t s, const BinsC* bins = nullptr) {
     const WsLayout L(n, cams ? 2 * int64_t(cams->n - 1) : 0);
     int32_t* counter = ws_at<int32_t>(ws, 0);
     HitRec* recs = ws_at<HitRec>(ws, L.recs);
@@ -974,9 +1100,9 @@ void trace_to_hits(const ModelC& c, const CamSet<NCAM>* cams, const float* ray_o
     int32_t* offsets = ws_at<int32_t>(ws, L.offsets);
     int32_t* runs = ws_at<int32_t>(ws, L.runs);
     TraceArgs a{ray_o, ray_d, n, rgba, depth, tri, ws_at<HitRec>(ws, L.tmp), blk};
-    const int n_blk = launch_trace(c, cams, a, n, s);
+    const int n_blk = launch_trace(c, cams, a, n, s, bins);
     const int n_runs = (n_blk + kScanRun - 1) / kScanRun;
-    hipLaunchKernelGGL(k_scan_local, dim3(n_runs), dim3(kScanThreads), 0, s, blk, n_blk, offsets, runs);
+    hipLaunchKernelGGL(k_scan_local, dim3(n_runs), dim3(kScanThreads), 0, s, reinterpret_cast<const int32_t*>(blk), 2, n_blk, offsets, runs, INT32_MAX);
     launch_check("k_scan_local");
     hipLaunchKernelGGL(k_scan_runs, dim3(1), dim3(kScanThreads), 0, s, runs, n_runs, counter, counter + 1,
                        kMaxChunks - 1);
@@ -1019,15 +1145,14 @@ AuxStream aux_stream(hipStream_t caller) {
 template <class TableT>
 void camera_range(const ModelC& c, int32_t precision, const CamSet<1>& cams, int t0, int t1, float* rgba,
                   float* depth, int32_t* tri, HitRec* tmp, int2* blk, int32_t* offsets, int32_t* runs, HitRec* recs,
-                  int32_t* counter, hipStream_t s) {
+                  int32_t* counter, hipStream_t s, const BinsC* bins) {
     CamSet<1> cs = cams;
     cs.c[0].tile0 = -t0;  // workgroup b traces tile t0 + b
     const int n_blk = t1 - t0;
     const TraceArgs a{nullptr, nullptr, 0, rgba, depth, tri, tmp, blk + t0};
-    hipLaunchKernelGGL((k_trace<true, 1>), dim3(n_blk), dim3(kThreads), 0, s, c, cs, a);
-    launch_check("k_trace");
+    launch_trace(c, &cs, a, 0, s, bins);
     const int n_runs = (n_blk + kScanRun - 1) / kScanRun;
-    hipLaunchKernelGGL(k_scan_local, dim3(n_runs), dim3(kScanThreads), 0, s, blk + t0, n_blk, offsets + t0, runs);
+    hipLaunchKernelGGL(k_scan_local, dim3(n_runs), dim3(kScanThreads), 0, s, reinterpret_cast<const int32_t*>(blk + t0), 2, n_blk, offsets + t0, runs, INT32_MAX);
     launch_check("k_scan_local");
     hipLaunchKernelGGL(k_scan_runs, dim3(1), dim3(kScanThreads), 0, s, runs, n_runs, counter, nullptr, 0);
     launch_check("k_scan_runs");
@@ -1045,7 +1170,7 @@ void camera_range(const ModelC& c, int32_t precision, const CamSet<1>& cams, int
 // two halves at int32 0 and 1.
 template <class TableT>
 void run_split(const ModelC& c, int32_t precision, const CamSet<1>& cams, float* rgba, float* depth, int32_t* tri,
-               void* ws, const WsLayout& L, hipStream_t s) {
+               void* ws, const WsLayout& L, hipStream_t s, const BinsC* bins) {
     const CamC& cam = cams.c[0];
     const int tiles_y = (cam.H + kTile - 1) / kTile, n_tiles = cam.tiles_x * tiles_y;
     const int tA = (tiles_y / 2) * cam.tiles_x;
@@ -1061,9 +1186,9 @@ void run_split(const ModelC& c, int32_t precision, const CamSet<1>& cams, float*
     hipStream_t s2 = aux.s2;
     check_hip(hipEventRecord(aux.fork, s), "hipEventRecord");
     check_hip(hipStreamWaitEvent(s2, aux.fork, 0), "hipStreamWaitEvent");
-    camera_range<TableT>(c, precision, cams, 0, tA, rgba, depth, tri, tmp, blk, offsets, runs, recs, counter, s);
+    camera_range<TableT>(c, precision, cams, 0, tA, rgba, depth, tri, tmp, blk, offsets, runs, recs, counter, s, bins);
     camera_range<TableT>(c, precision, cams, tA, n_tiles, rgba, depth, tri, tmp, blk, offsets, runs + runsA,
-                         recs + nA, counter + 1, s2);
+                         recs + nA, counter + 1, s2, bins);
     check_hip(hipEventRecord(aux.join, s2), "hipEventRecord");
     check_hip(hipStreamWaitEvent(s, aux.join, 0), "hipStreamWaitEvent");
 }
@@ -1088,17 +1213,24 @@ void run_path(const inrf_model* m, int32_t precision, const CamSet<NCAM>* cams, 
         fail(INRF_E_SIZE, "workspace of " + std::to_string(ws_bytes) + " bytes < " + std::to_string(L.end) +
                               " needed");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // a single camera's frame is traced through screen bins of the proxy
+    BinsC bins_v;
+    const BinsC* bins = nullptr;
+    if constexpr (NCAM == 1) {
+        if (cams && make_bins(cams->c[0], ws, L, bins_v)) bins = &bins_v;
+    }
+    record(events, 0, s);
+    if (bins) bin_frame(c, *bins, s);
     if constexpr (NCAM == 1) {
         if (split && cams && !events && (cams->c[0].H + kTile - 1) / kTile >= kSplitTileRows) {
-            if (c.table_dtype == INRF_F32) run_split<float>(c, precision, *cams, rgba, depth, tri, ws, L, s);
-            else run_split<__half>(c, precision, *cams, rgba, depth, tri, ws, L, s);
+            if (c.table_dtype == INRF_F32) run_split<float>(c, precision, *cams, rgba, depth, tri, ws, L, s, bins);
+            else run_split<__half>(c, precision, *cams, rgba, depth, tri, ws, L, s, bins);
             return;
         }
     }
     const int32_t* counter = ws_at<int32_t>(ws, 0);
     const HitRec* recs = ws_at<HitRec>(ws, L.recs);
-    record(events, 0, s);
-    trace_to_hits(c, cams, ray_o, ray_d, n, rgba, depth, tri, ws, s);
+    trace_to_hits(c, cams, ray_o, ray_d, n, rgba, depth, tri, ws, s, bins);
     record(events, 1, s);
     if (c.table_dtype == INRF_F32) launch_shade<float>(c, precision, recs, nullptr, counter, rgba, s);
     else launch_shade<__half>(c, precision, recs, nullptr, counter, rgba, s);
@@ -1302,7 +1434,7 @@ void run_scene(const inrf_instance* objects, int32_t n_objs, int32_t precision, 
     if (n_objs == 0) return;
     const int n_blk = n_objs * n_tiles;
     const int n_runs = (n_blk + kScanRun - 1) / kScanRun;
-    hipLaunchKernelGGL(k_scan_local, dim3(n_runs), dim3(kScanThreads), 0, s, blk, n_blk, offsets, runs);
+    hipLaunchKernelGGL(k_scan_local, dim3(n_runs), dim3(kScanThreads), 0, s, reinterpret_cast<const int32_t*>(blk), 2, n_blk, offsets, runs, INT32_MAX);
     launch_check("k_scan_local");
     hipLaunchKernelGGL(k_scan_runs, dim3(1), dim3(kScanThreads), 0, s, runs, n_runs, counter, counter + 1,
                        kMaxChunks - 1);
@@ -1414,7 +1546,7 @@ void run_nolf(const inrf_model* m, const inrf_cubes* cubes, int32_t precision, c
     hipLaunchKernelGGL(k_march, dim3(n_blk), dim3(kThreads), 0, s, C, cam, a);
     launch_check("k_march");
     const int n_runs = (n_blk + kScanRun - 1) / kScanRun;
-    hipLaunchKernelGGL(k_scan_local, dim3(n_runs), dim3(kScanThreads), 0, s, blk, n_blk, offsets, runs);
+    hipLaunchKernelGGL(k_scan_local, dim3(n_runs), dim3(kScanThreads), 0, s, reinterpret_cast<const int32_t*>(blk), 2, n_blk, offsets, runs, INT32_MAX);
     launch_check("k_scan_local");
     hipLaunchKernelGGL(k_scan_runs, dim3(1), dim3(kScanThreads), 0, s, runs, n_runs, counter, counter + 1,
                        kMaxChunks - 1);
@@ -1595,7 +1727,7 @@ inrf_status inrf_trace(const inrf_model* m, const float* ray_o, const float* ray
         require(n == 0 || (ray_o && ray_d && tri && t), "NULL buffer");
         if (n == 0) return;
         const dev::TraceArgs a{ray_o, ray_d, n, nullptr, t, tri, nullptr, nullptr};  // no records
-        launch_trace<1>(c, nullptr, a, n, reinterpret_cast<hipStream_t>(stream));
+        launch_trace<1>(c, nullptr, a, n, reinterpret_cast<hipStream_t>(stream), nullptr);
     });
 }
 

@@ -107,3 +107,70 @@ def test_empty_scene_and_errors(scene):
     with pytest.raises(P.InrfError):
         neg.render(cam)
     assert P.lib().inrf_scene_workspace_size(17, 100) == -1
+
+
+@pytest.fixture(scope="module")
+def scene12():
+    """The benchmark's scene: 12 displaced spheres (32,000 triangles each, own
+    features and networks, 10 levels 16..512), scale 0.2-1.0 in a 4^3 box,
+    rendered at 3840x2160."""
+    import paper_2303_04086_amd as P
+    sc = synth.scene_objects(12, 3840, 2160)
+    rs = [make_renderer(o.workload, tables=("f32", "f16")) for o in sc.objects]
+    S = P.Scene(rs, [(o.scale, o.rotation, o.translation) for o in sc.objects])
+    insts = []
+    for o in sc.objects:
+        s, R, t = _placement32(o)
+        insts.append(Instance(oracle.Model.from_workload(o.workload, materialize=False, check_keys=False), s, R, t))
+    return sc, S, insts
+
+
+def _scene_pixels(sc, cam, n_near, n_any, seed):
+    """n_near pixels whose FP64 ray passes through some object's bounding
+    ball (centre s R (0.5, 0.5, 0.5) + t, radius s / 2), then n_any uniform
+    pixels; chosen from the camera and the placements alone."""
+    rng = np.random.default_rng(seed)
+    pool = rng.integers(0, cam.width * cam.height, 60 * n_near + 1000)
+    o, d = oracle.camera_rays(cam, pool // cam.width, pool % cam.width)
+    d = d / np.linalg.norm(d, axis=1, keepdims=True)
+    near = np.zeros(len(pool), bool)
+    for ob in sc.objects:
+        c = ob.scale * np.asarray(ob.rotation) @ np.full(3, 0.5) + np.asarray(ob.translation)
+        v = c - o
+        tca = np.sum(v * d, axis=1)
+        near |= (np.sum(v * v, axis=1) - tca ** 2 < (0.5 * ob.scale) ** 2) & (tca > 0)
+    sel = pool[near][:n_near]
+    assert len(sel) == n_near
+    return np.concatenate([sel, rng.integers(0, cam.width * cam.height, n_any)])
+
+
+@pytest.mark.parametrize("cam_id", [0, 5])
+def test_scene12_4k_sampled(scene12, cam_id):
+    """The 12-object scene at 4K in the launch configuration the benchmark
+    times, on 400 sampled pixels: object and triangle ids bit-exact on
+    unambiguous rays, FP32 colour to 1e-5, FP16 to 2e-3 with PSNR >= 50 dB
+    over hit pixels."""
+    from gpu_helpers import psnr
+    sc, S, insts = scene12
+    cam = sc.cameras[cam_id]
+    rgba, depth, tri, obj = _render(S, cam)
+    rgba16 = _render(S, cam, "fp16", "f16")[0]
+    pix = _scene_pixels(sc, cam, 320, 80, 40 + cam_id)
+    o, d = oracle.camera_rays(cam, pix // cam.width, pix % cam.width)
+    ora = render_scene_rays(insts, o, d, **EPS)
+    clear = ~ora["ambiguous"]
+    bad = np.nonzero(clear & ((obj[pix] != ora["obj"]) | (tri[pix] != ora["tri"])))[0]
+    assert len(bad) == 0, (pix[bad[:5]], obj[pix][bad[:5]], ora["obj"][bad[:5]])
+    agree = obj[pix] == ora["obj"]
+    hit = agree & (ora["obj"] >= 0)
+    per_obj = np.bincount(ora["obj"][ora["obj"] >= 0], minlength=12)
+    e32 = np.abs(rgba[pix][agree] - ora["rgba"][agree]).max()
+    e16 = np.abs(rgba16[pix][agree] - ora["rgba"][agree]).max()
+    p16 = psnr(rgba16[pix][hit], ora["rgba"][hit])
+    print(f"scene12 camera {cam_id}: {int(hit.sum())} sampled hits over {int((per_obj > 0).sum())} objects, "
+          f"ambiguous {int(ora['ambiguous'].sum())}, fp32 {e32:.2e}, fp16 {e16:.2e} ({p16:.1f} dB)")
+    assert hit.sum() >= 200 and (per_obj > 0).sum() >= 4
+    assert ora["ambiguous"].mean() <= 0.01
+    assert e32 <= 1e-5
+    assert e16 <= 2e-3 and p16 >= 50.0
+    assert np.allclose(depth[pix][hit & clear], ora["t"][hit & clear], rtol=1e-5, atol=0)
