@@ -25,6 +25,17 @@
 // goes into a global list that every quadrant tests.  A quadrant whose list
 // did not fit the workspace, or every quadrant when the global list
 // overflows, walks the BVH instead.
+//
+// Depth skip.  A quadrant's list holds the triangles facing the camera
+// first, then the others, each with a lower bound on the distance t at which
+// any camera ray can meet it: a point p of the triangle lies at t = |p - o|
+// >= lambda(p) / |a_f| >= min_i lambda(v_i) / |a_f| (a_f the lambda row of
+// A, unit rays), widened by 1e-4 for the FP32 rounding of lambda and of the
+// test's t.  After the facing triangles, a wave skips every further
+// triangle whose bound exceeds the largest closest hit among its rays: such
+// a triangle can only be met farther than every ray's hit, so skipping it
+// changes nothing.  On a closed proxy seen from outside this skips most of
+// the triangles facing away.
 #pragma once
 
 namespace inrf {
@@ -40,14 +51,15 @@ struct BinsC {
     float o[3];                // camera centre
     float sjx, sjb, siy, sib;  // pixel column j = X / lambda * sjx + sjb, row i = Y / lambda * siy + sib
     int32_t W, H, QX, QY;      // image and quadrant grid sizes
-    int32_t* cnt;              // [QX * QY] entries per quadrant (the fill pass counts them back to 0)
+    int32_t* cnt;              // [QX * QY] entries per quadrant (the fill pass counts the others back down)
+    int32_t* fcnt;             // [QX * QY] facing entries per quadrant (counted up by the fill pass)
     int32_t* off;              // [QX * QY] exclusive offsets within scan runs
     int32_t* runs;             // scan run carries
     int32_t* total;            // total entries, then the global list: total[1] = its count, total[2 ..] records
-    int32_t* entries;          // [E] triangle records, quadrant after quadrant
+    int2* entries;             // [E] (triangle record, bits of its distance bound), quadrant after quadrant
     int64_t E;
     int32_t clamp;             // the scan adds min(count, clamp) per quadrant, so sums fit 31 bits
-    int32_t pad;
+    float tscale;              // (1 - 1e-4) / |a_f|: distance bound per unit of lambda
 };
 
 // Quadrant q's list [s, e) and whether it holds every record of the quadrant:
@@ -62,15 +74,20 @@ __device__ __forceinline__ bool bin_list(const BinsC& b, int q, int64_t& s, int6
 // Quadrant range of triangle record k: 0 = no pixel can hit it, 1 = the
 // range [qx0, qx1] x [qy0, qy1], 2 = the global list.
 __device__ __forceinline__ int bin_range(const BinsC& b, const BvhTri* __restrict__ tris, int64_t k, int& qx0,
-                                         int& qx1, int& qy0, int& qy1) {
+                                         int& qx1, int& qy0, int& qy1, bool* facing = nullptr,
+                                         float* lam_min = nullptr) {
 #pragma clang fp contract(off)  // the count and fill passes must classify every triangle identically
     const float4* p = reinterpret_cast<const float4*>(tris + k);
     const float4 v[3] = {p[0], p[1], p[2]};
-    float jlo = INFINITY, jhi = -INFINITY, ilo = INFINITY, ihi = -INFINITY;
+    float jlo = INFINITY, jhi = -INFINITY, ilo = INFINITY, ihi = -INFINITY, lmin = INFINITY;
     int front = 0, behind = 0;
+    float qv[3][3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const float qx = v[c].x - b.o[0], qy = v[c].y - b.o[1], qz = v[c].z - b.o[2];
+        qv[c][0] = qx;
+        qv[c][1] = qy;
+        qv[c][2] = qz;
         const float X = b.a[0] * qx + b.a[1] * qy + b.a[2] * qz;
         const float Y = b.a[3] * qx + b.a[4] * qy + b.a[5] * qz;
         const float lam = b.a[6] * qx + b.a[7] * qy + b.a[8] * qz;
@@ -83,6 +100,14 @@ __device__ __forceinline__ int bin_range(const BinsC& b, const BvhTri* __restric
         jhi = fmaxf(jhi, j);
         ilo = fminf(ilo, i);
         ihi = fmaxf(ihi, i);
+        lmin = fminf(lmin, lam);
+    }
+    if (lam_min) *lam_min = lmin;
+    if (facing) {  // normal (v1 - v0) x (v2 - v0) against the view from the centre
+        const float e1[3] = {qv[1][0] - qv[0][0], qv[1][1] - qv[0][1], qv[1][2] - qv[0][2]};
+        const float e2[3] = {qv[2][0] - qv[0][0], qv[2][1] - qv[0][1], qv[2][2] - qv[0][2]};
+        const float n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        *facing = n[0] * qv[0][0] + n[1] * qv[0][1] + n[2] * qv[0][2] <= 0.f;
     }
     if (behind == 3) return 0;
     if (front != 3) return 2;
@@ -101,19 +126,27 @@ __device__ __forceinline__ int bin_range(const BinsC& b, const BvhTri* __restric
 // Clears the quadrant counts and the global list (one thread per quadrant).
 __global__ void k_bin_clear(BinsC b) {
     const int q = int(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (q < b.QX * b.QY) b.cnt[q] = 0;
+    if (q < b.QX * b.QY) {
+        b.cnt[q] = 0;
+        b.fcnt[q] = 0;
+    }
     if (q == 0) b.total[1] = 0;
 }
 
 // Count pass (FILL = false) and fill pass (FILL = true), one thread per
-// triangle record.  The fill pass counts each quadrant back down to zero and
-// stores records only in quadrants whose whole list was kept (bin_list).
+// triangle record.  The fill pass stores a quadrant's facing triangles from
+// the start of its list up (counting fcnt up) and the others from the end
+// down (counting cnt down), only in quadrants whose whole list was kept
+// (bin_list).
 template <bool FILL>
 __global__ __launch_bounds__(256) void k_bin(BinsC b, const BvhTri* __restrict__ tris, int64_t n_tris) {
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= n_tris) return;
     int qx0, qx1, qy0, qy1;
-    const int r = bin_range(b, tris, k, qx0, qx1, qy0, qy1);
+    bool facing = true;
+    float lmin = 0.f;
+    const int r = bin_range(b, tris, k, qx0, qx1, qy0, qy1, FILL ? &facing : nullptr, FILL ? &lmin : nullptr);
+    const int2 rec = make_int2(int32_t(k), __float_as_int(lmin * b.tscale));
     if (r == 0) return;
     if (r == 2) {
         if (!FILL) {
@@ -130,8 +163,8 @@ __global__ __launch_bounds__(256) void k_bin(BinsC b, const BvhTri* __restrict__
             } else {
                 int64_t s, e;
                 const bool whole = bin_list(b, q, s, e);
-                const int slot = atomicSub(b.cnt + q, 1) - 1;
-                if (whole && slot >= 0 && s + slot < e) b.entries[s + slot] = int32_t(k);
+                const int slot = facing ? atomicAdd(b.fcnt + q, 1) : atomicSub(b.cnt + q, 1) - 1;
+                if (whole && slot >= 0 && s + slot < e) b.entries[s + slot] = rec;
             }
         }
 }
@@ -149,17 +182,33 @@ __device__ __forceinline__ void bin_test(const RayPre& R, const BvhTri* __restri
     best_i = better ? idx : best_i;
 }
 
-// Records [s, e) of a quadrant's list against the wave's rays, with the
-// axes of the watertight test given by Ax.  Four records, then their four
-// triangles, are requested before any test waits on them.
-template <class Ax>
-__device__ __forceinline__ void bin_walk(const RayPre& R, const Ax& ax, const int32_t* __restrict__ ent,
-                                         const float4* __restrict__ tv, int s, int e, bool active, float& best_t,
-                                         int32_t& best_i) {
+// Largest closest-hit distance over the wave's active rays (+inf if one of
+// them has no hit yet).
+__device__ __forceinline__ float wave_max_best(bool active, float best_t) {
+    float m = active ? best_t : -INFINITY;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) m = fmaxf(m, __shfl_xor(m, d));
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(m)));  // the same in every lane
+}
+
+// Entries [s, e) of a quadrant's list against the wave's rays, with the axes
+// of the watertight test given by Ax, four at a time: the four records, then
+// their triangles, are requested before any test waits on them.  With SKIP,
+// entries whose distance bound exceeds tmax are not tested.
+template <bool SKIP, class Ax>
+__device__ __forceinline__ void bin_walk(const RayPre& R, const Ax& ax, const int2* __restrict__ ent,
+                                         const float4* __restrict__ tv, int s, int e, float tmax, bool active,
+                                         float& best_t, int32_t& best_i) {
     for (int k = s; k < e; k += 4) {
         int32_t r[4];
+        bool go[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) r[u] = __builtin_amdgcn_readfirstlane(ent[k + u < e ? k + u : k]);
+        for (int u = 0; u < 4; ++u) {
+            const int2 en = ent[k + u < e ? k + u : k];
+            r[u] = __builtin_amdgcn_readfirstlane(en.x);
+            go[u] = !SKIP || !(__int_as_float(__builtin_amdgcn_readfirstlane(en.y)) > tmax);
+        }
+        if (SKIP && !(go[0] || go[1] || go[2] || go[3])) continue;
         float4 v[12];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
@@ -167,6 +216,7 @@ __device__ __forceinline__ void bin_walk(const RayPre& R, const Ax& ax, const in
             for (int c = 0; c < 3; ++c) v[3 * u + c] = tv[3 * int64_t(r[u]) + c];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
+            if (!go[u]) continue;  // wave-uniform
             const float t = hit_triangle_ax(R, ax, make_float3(v[3 * u].x, v[3 * u].y, v[3 * u].z),
                                             make_float3(v[3 * u + 1].x, v[3 * u + 1].y, v[3 * u + 1].z),
                                             make_float3(v[3 * u + 2].x, v[3 * u + 2].y, v[3 * u + 2].z));
@@ -176,6 +226,15 @@ __device__ __forceinline__ void bin_walk(const RayPre& R, const Ax& ax, const in
             best_i = better ? idx : best_i;
         }
     }
+}
+
+// The facing part of a quadrant's list, then the rest with the depth skip.
+template <class Ax>
+__device__ __forceinline__ void bin_walk_list(const RayPre& R, const Ax& ax, const int2* __restrict__ ent,
+                                              const float4* __restrict__ tv, int s, int f, int e, bool active,
+                                              float& best_t, int32_t& best_i) {
+    bin_walk<false>(R, ax, ent, tv, s, f, INFINITY, active, best_t, best_i);
+    if (f < e) bin_walk<true>(R, ax, ent, tv, f, e, wave_max_best(active, best_t), active, best_t, best_i);
 }
 
 // Closest hit of a wave of camera rays in quadrant (qx, qy) through its
@@ -197,9 +256,12 @@ __device__ void closest_hit_binned(const B& m, const BinsC& b, int qx, int qy, c
         closest_hit_packet(m, R, active, wst, best_t, best_i);
         return;
     }
+    // the global list first: its triangles have no distance bound
+    for (int k = 0; k < g; ++k) bin_test(R, m.tris, __builtin_amdgcn_readfirstlane(b.total[2 + k]), active, best_t, best_i);
     // lists lie in [0, E) with E < 2^31 records, so 32-bit bounds suffice
     const int s = __builtin_amdgcn_readfirstlane(int(s64)), e = __builtin_amdgcn_readfirstlane(int(e64));
-    const int32_t* __restrict__ ent = b.entries;
+    const int f = min(e, s + __builtin_amdgcn_readfirstlane(b.fcnt[q]));
+    const int2* __restrict__ ent = b.entries;
     const float4* __restrict__ tv = reinterpret_cast<const float4*>(m.tris);
     // permutation id: kz (0..2) and whether kx, ky were swapped
     const int perm = 2 * R.kz + (R.kx == (R.kz + 1) % 3 ? 0 : 1);
@@ -207,17 +269,16 @@ __device__ void closest_hit_binned(const B& m, const BinsC& b, int qx, int qy, c
     const int pu = __builtin_amdgcn_readlane(perm, lead);
     if (__ballot(active && perm != pu) == 0) {
         switch (pu) {
-            case 0: bin_walk(R, AxisC<1, 2, 0>(), ent, tv, s, e, active, best_t, best_i); break;
-            case 1: bin_walk(R, AxisC<2, 1, 0>(), ent, tv, s, e, active, best_t, best_i); break;
-            case 2: bin_walk(R, AxisC<2, 0, 1>(), ent, tv, s, e, active, best_t, best_i); break;
-            case 3: bin_walk(R, AxisC<0, 2, 1>(), ent, tv, s, e, active, best_t, best_i); break;
-            case 4: bin_walk(R, AxisC<0, 1, 2>(), ent, tv, s, e, active, best_t, best_i); break;
-            default: bin_walk(R, AxisC<1, 0, 2>(), ent, tv, s, e, active, best_t, best_i); break;
+            case 0: bin_walk_list(R, AxisC<1, 2, 0>(), ent, tv, s, f, e, active, best_t, best_i); break;
+            case 1: bin_walk_list(R, AxisC<2, 1, 0>(), ent, tv, s, f, e, active, best_t, best_i); break;
+            case 2: bin_walk_list(R, AxisC<2, 0, 1>(), ent, tv, s, f, e, active, best_t, best_i); break;
+            case 3: bin_walk_list(R, AxisC<0, 2, 1>(), ent, tv, s, f, e, active, best_t, best_i); break;
+            case 4: bin_walk_list(R, AxisC<0, 1, 2>(), ent, tv, s, f, e, active, best_t, best_i); break;
+            default: bin_walk_list(R, AxisC<1, 0, 2>(), ent, tv, s, f, e, active, best_t, best_i); break;
         }
     } else {
-        bin_walk(R, AxisR{R.kx, R.ky, R.kz}, ent, tv, s, e, active, best_t, best_i);
+        bin_walk_list(R, AxisR{R.kx, R.ky, R.kz}, ent, tv, s, f, e, active, best_t, best_i);
     }
-    for (int k = 0; k < g; ++k) bin_test(R, m.tris, __builtin_amdgcn_readfirstlane(b.total[2 + k]), active, best_t, best_i);
 }
 
 }  // namespace dev

@@ -773,14 +773,14 @@ constexpr int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
 // tiles.
 struct WsLayout {
     int64_t recs, tmp, blk, offsets, runs;
-    int64_t qcnt, qoff, qruns, qtotal, entries;  // screen bins of a camera frame (bin_device.hpp)
+    int64_t qcnt, qfcnt, qoff, qruns, qtotal, entries;  // screen bins of a camera frame (bin_device.hpp)
     int64_t n_quads, n_entries, end;
     // extra: 2 more tiles per additional camera of a batch.  A W x H = n
     // pixel frame has ceil(W/8) ceil(H/8) <= n/8 + 1 quadrants; the bins
-    // hold up to 2n triangle records (a quadrant whose list does not fit
+    // hold up to n triangle records (a quadrant whose list does not fit
     // walks the BVH instead).
     constexpr explicit WsLayout(int64_t n, int64_t extra = 0)
-        : recs(0), tmp(0), blk(0), offsets(0), runs(0), qcnt(0), qoff(0), qruns(0), qtotal(0), entries(0),
+        : recs(0), tmp(0), blk(0), offsets(0), runs(0), qcnt(0), qfcnt(0), qoff(0), qruns(0), qtotal(0), entries(0),
           n_quads(0), n_entries(0), end(0) {
         const int64_t nb = n / 8 + 2 + extra, nr = nb / kScanRun + 1 + kMaxChunks;
         recs = kWsHeader;
@@ -789,13 +789,14 @@ struct WsLayout {
         offsets = align256(blk + nb * int64_t(sizeof(int2)));
         runs = align256(offsets + nb * int64_t(sizeof(int32_t)));
         n_quads = n / 8 + 1;
-        n_entries = 2 * n;
+        n_entries = n;
         qcnt = align256(runs + nr * int64_t(sizeof(int32_t)));
-        qoff = align256(qcnt + n_quads * int64_t(sizeof(int32_t)));
+        qfcnt = align256(qcnt + n_quads * int64_t(sizeof(int32_t)));
+        qoff = align256(qfcnt + n_quads * int64_t(sizeof(int32_t)));
         qruns = align256(qoff + n_quads * int64_t(sizeof(int32_t)));
         qtotal = align256(qruns + (n_quads / kScanRun + 2) * int64_t(sizeof(int32_t)));
         entries = align256(qtotal + (2 + kBinGlobal) * int64_t(sizeof(int32_t)));
-        end = align256(entries + n_entries * int64_t(sizeof(int32_t)));
+        end = align256(entries + n_entries * int64_t(sizeof(int2)));
     }
 };
 
@@ -1027,11 +1028,15 @@ bool make_bins(const CamC& cam, void* ws, const WsLayout& L, BinsC& b) {
     b.QY = (cam.H + kQuad - 1) / kQuad;
     if (int64_t(b.QX) * b.QY > L.n_quads) return false;
     b.cnt = ws_at<int32_t>(ws, L.qcnt);
+    b.fcnt = ws_at<int32_t>(ws, L.qfcnt);
     b.off = ws_at<int32_t>(ws, L.qoff);
     b.runs = ws_at<int32_t>(ws, L.qruns);
     b.total = ws_at<int32_t>(ws, L.qtotal);
-    b.entries = ws_at<int32_t>(ws, L.entries);
+    b.entries = ws_at<int2>(ws, L.entries);
     b.E = L.n_entries;
+    // distance bound per unit of lambda: t >= lambda / |a_f| for unit rays
+    const double af = std::sqrt(double(b.a[6]) * b.a[6] + double(b.a[7]) * b.a[7] + double(b.a[8]) * b.a[8]);
+    b.tscale = float((1.0 - 1e-4) / af);
     b.clamp = int32_t(std::min<int64_t>(L.n_entries + 1, ((int64_t(1) << 31) - 1) / (int64_t(b.QX) * b.QY)));
     return true;
 }
