@@ -52,22 +52,19 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def run_frames(torch, R, cams, prec, table, steps, warmup, split=True):
-    """Timed frames, then the same frames through the stage-event entry
-    point.  The timed pass calls inrf_render, which renders a frame of 8 or
-    more tile rows as two halves on two streams (`split`; otherwise it goes
-    through the stage-event entry point, which never splits); per-frame
-    events on the caller's stream bracket each call.  The stage pass records
-    trace start, shading start and end on the kernels' stream of an unsplit
-    frame: the trace / shade breakdown and the shading launch time of the
-    roofline object come from it."""
+def run_frames(torch, R, cams, prec, table, steps, warmup):
+    """Timed frames (one inrf_render each, per-frame events on the caller's
+    stream around each call), then the same frames through the stage-event
+    entry point, which records trace start, shading start and end on the
+    kernels' stream: the trace / shade breakdown and the shading launch time
+    of the roofline object come from that pass."""
     rgba = torch.empty((cams[0].height, cams[0].width, 4), dtype=torch.float32, device="cuda")
     for i in range(warmup):
-        R.render(cams[i % len(cams)], prec, table, rgba=rgba, split=split)
+        R.render(cams[i % len(cams)], prec, table, rgba=rgba)
     torch.cuda.synchronize()
     hits = []
     for c in cams:
-        R.render(c, prec, table, rgba=rgba, split=split)
+        R.render(c, prec, table, rgba=rgba)
         torch.cuda.synchronize()
         hits.append(R.hit_count())
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
@@ -78,27 +75,20 @@ def run_frames(torch, R, cams, prec, table, steps, warmup, split=True):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
-        if split:
-            fr[i][0].record()
-            R.render(cams[i % len(cams)], prec, table, rgba=rgba)
-            fr[i][1].record()
-        else:
-            R.render(cams[i % len(cams)], prec, table, rgba=rgba, events=ev[i])
+        fr[i][0].record()
+        R.render(cams[i % len(cams)], prec, table, rgba=rgba)
+        fr[i][1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    frame = [fr[i][0].elapsed_time(fr[i][1]) for i in range(steps)] if split else None
-    t1 = time.perf_counter()
-    if split:
-        for i in range(steps):
-            R.render(cams[i % len(cams)], prec, table, rgba=rgba, events=ev[i])
-        torch.cuda.synchronize()
-    stage_wall = time.perf_counter() - t1 if split else wall
-    unsplit = [ev[i][0].elapsed_time(ev[i][2]) for i in range(steps)]
+    frame = [fr[i][0].elapsed_time(fr[i][1]) for i in range(steps)]
+    for i in range(steps):
+        R.render(cams[i % len(cams)], prec, table, rgba=rgba, events=ev[i])
+    torch.cuda.synchronize()
     trace = [ev[i][0].elapsed_time(ev[i][1]) for i in range(steps)]
     shade = [ev[i][1].elapsed_time(ev[i][2]) for i in range(steps)]
     shade_hits = [hits[i % len(cams)] for i in range(steps)]
-    return {"wall_s": wall, "frame_ms": frame or unsplit, "unsplit_ms": unsplit, "stage_wall_s": stage_wall,
-            "trace_ms": trace, "shade_ms": shade, "hits": shade_hits, "hits_per_camera": hits, "split": split}
+    return {"wall_s": wall, "frame_ms": frame, "trace_ms": trace, "shade_ms": shade, "hits": shade_hits,
+            "hits_per_camera": hits}
 
 
 def pct(v, q):
@@ -121,9 +111,6 @@ def summarize(r, W, H, steps, n_levels, table):
         "hit_rays_per_frame_avg": round(sum(r["hits"]) / steps, 1),
         "hit_Mrays_per_s": round(sum(r["hits"]) / r["wall_s"] / 1e6, 2),
         "shade_requested_GBps": round(achieved, 1),
-        "split_frames": r["split"],
-        "unsplit_Mrays_per_s": round(rays / r["stage_wall_s"] / 1e6, 2),
-        "unsplit_p50_ms": round(pct(r["unsplit_ms"], 50), 4),
     }
 
 
@@ -146,28 +133,120 @@ def mlp_bench(torch, R, prec, n, reps=5):
             "utilisation": round(tf / MFMA_PEAK_TFLOPS[prec], 4)}
 
 
-def cpu_baseline(w, n_sample, seed=11):
-    """The FP64 oracle, as it stands, on a seeded sample of pixels of camera 0."""
+_ORACLE = {}
+
+
+def _oracle_task(idx):
+    """Worker of the multi-core oracle run: FP64 path on the listed rays."""
+    import oracle
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        r = oracle.render_rays(_ORACLE["model"], _ORACLE["o"][idx], _ORACLE["d"][idx], eps_bary=1e-4)
+        dt = time.perf_counter() - t0
+    return idx, r["rgba"], r["tri"], r["ambiguous"], dt
+
+
+def disc_pixels(cam, n_near, n_any, seed, centre=(0.5, 0.5, 0.5), radius=0.5):
+    """n_near pixels whose FP64 ray passes within `radius` of the object's
+    centre (the proxy lies in that ball, so most of them hit), then n_any
+    uniform pixels: chosen from the camera geometry alone."""
     import numpy as np
     import oracle
-    try:
-        from threadpoolctl import threadpool_limits
-        limiter = threadpool_limits(1)
-    except Exception:  # pragma: no cover
-        limiter = None
-    cam = w.cameras[0]
     rng = np.random.default_rng(seed)
-    rows = rng.integers(0, cam.height, n_sample)
-    cols = rng.integers(0, cam.width, n_sample)
-    m = oracle.Model.from_workload(w, materialize=False, check_keys=False)
-    t0 = time.perf_counter()
-    oracle.render_camera(m, cam, rows, cols)
-    dt = time.perf_counter() - t0
-    if limiter is not None:
-        limiter.unregister() if hasattr(limiter, "unregister") else None
-    return {"value": round(n_sample / dt / 1e6, 6), "unit": "Mrays/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_sample} seeded random pixels of camera 0 at {cam.width}x{cam.height}, "
-                      f"full path in FP64 ({dt:.1f} s)"}
+    pool = rng.integers(0, cam.width * cam.height, 12 * n_near + 1000)
+    o, d = oracle.camera_rays(cam, pool // cam.width, pool % cam.width)
+    d = d / np.linalg.norm(d, axis=1, keepdims=True)
+    v = np.asarray(centre) - o
+    tca = np.sum(v * d, axis=1)
+    near = pool[(np.sum(v * v, axis=1) - tca ** 2 < radius ** 2) & (tca > 0)][:n_near]
+    return np.concatenate([near, rng.integers(0, cam.width * cam.height, n_any)])
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, n_near, n_any, n_one, seed=11):
+    """The FP64 oracle, as it stands, on the host cores, before anything
+    touches the GPU: a seeded sample of pixels of camera 0 (n_near near the
+    object, n_any uniform) split over worker processes (one BLAS thread
+    each), the first n_one of them again on one core, and the tiny
+    workload's full 64x64 frame on one core.  Its outputs are kept: they are
+    the FP64 reference of the GPU frames' error figures."""
+    import multiprocessing as mp
+    import numpy as np
+    import oracle
+    import synth
+    from threadpoolctl import threadpool_limits
+    cam = w.cameras[0]
+    pix = disc_pixels(cam, n_near, n_any, seed)
+    o, d = oracle.camera_rays(cam, pix // cam.width, pix % cam.width)
+    _ORACLE.update(model=oracle.Model.from_workload(w, materialize=False, check_keys=False), o=o, d=d)
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        _oracle_task(np.arange(n_one))
+        dt1 = time.perf_counter() - t0
+        ctx = mp.get_context("fork")
+        with ctx.Pool(cores) as pool:
+            pool.map(_oracle_task, [np.arange(0, 1)] * cores)  # workers up
+            chunks = np.array_split(np.arange(len(pix)), 8 * cores)
+            t0 = time.perf_counter()
+            res = pool.map(_oracle_task, chunks)
+            dtk = time.perf_counter() - t0
+        wt = synth.workload_tiny()
+        mt = oracle.Model.from_workload(wt)
+        t0 = time.perf_counter()
+        oracle.render_camera(mt, wt.cameras[0])
+        dtw1 = time.perf_counter() - t0
+    rgba = np.zeros((len(pix), 4))
+    tri = np.zeros(len(pix), np.int64)
+    amb = np.zeros(len(pix), bool)
+    for idx, r, t, a, _ in res:
+        rgba[idx], tri[idx], amb[idx] = r, t, a
+    ref = {"pix": pix, "rgba": rgba, "tri": tri, "ambiguous": amb}
+    base = {"value": round(len(pix) / dtk / 1e6, 6), "unit": "Mrays/s", "cores": cores, "kind": "oracle",
+            "cpu": cpu_model(),
+            "sample": f"{len(pix)} seeded pixels of camera 0 at {cam.width}x{cam.height} ({n_near} chosen near the "
+                      f"object, {n_any} uniform; hit fraction {float((tri >= 0).mean()):.3f}), full path in FP64 "
+                      f"over {cores} processes ({dtk:.1f} s)",
+            "one_core": {"value": round(n_one / dt1 / 1e6, 6), "rays": n_one, "s": round(dt1, 2)},
+            "full_frame_4k_extrapolated_s": round(cam.width * cam.height / (len(pix) / dtk), 1),
+            "tiny_full_frame": {"workload": wt.name, "rays": 64 * 64, "s": round(dtw1, 2),
+                                "Mrays_per_s": round(64 * 64 / dtw1 / 1e6, 6), "cores": 1}}
+    return base, ref
+
+
+def frame_errors(torch, R, cam, ref, cases):
+    """Error of the GPU frames of camera 0 against the FP64 oracle on the
+    sampled pixels: max abs over pixels whose hit/miss agrees (every
+    disagreement must be a ray the oracle flags ambiguous), PSNR over the
+    pixels hit by either side."""
+    import numpy as np
+    out = {}
+    n = cam.width * cam.height
+    for prec, table in cases:
+        tri = torch.empty(n, dtype=torch.int32, device="cuda")
+        rgba = R.render(cam, prec, table, tri=tri).reshape(-1, 4).cpu().numpy()[ref["pix"]]
+        tri = tri.cpu().numpy()[ref["pix"]]
+        agree = (tri >= 0) == (ref["tri"] >= 0)
+        clear = ~ref["ambiguous"]
+        hit = agree & ((tri >= 0) | (ref["tri"] >= 0))
+        mse = float(np.mean((rgba[hit] - ref["rgba"][hit]) ** 2))
+        out[prec] = {"max_abs": float(f"{np.abs(rgba[agree] - ref['rgba'][agree]).max():.3e}"),
+                     "psnr_db": float(round(10 * np.log10(1.0 / mse), 1)) if mse > 0 else None,
+                     "pixels": int(len(tri)), "hit_pixels": int(hit.sum()),
+                     "ids_bit_exact": bool(np.array_equal(tri[clear], ref["tri"][clear])),
+                     "disagreements_all_ambiguous": bool(np.all(agree | ref["ambiguous"]))}
+    return out
 
 
 def load_traffic(kernel: str):
@@ -341,7 +420,7 @@ def nolf_bench(torch, P, frames, W, H):
 
 
 def graph_bench(torch, P, R, frames=200):
-    """One 1920x1080 camera at distance 2, FP16: eager unsplit renders (one
+    """One 1920x1080 camera at distance 2, FP16: eager renders (one
     library call each) against replays of the same render captured as a
     HIP graph; wall time over the frames between two synchronisations."""
     import synth
@@ -352,16 +431,16 @@ def graph_bench(torch, P, R, frames=200):
     rgba = torch.empty((cam.height, cam.width, 4), device="cuda")
     for mode in ("eager", "graph"):
         for _ in range(5):
-            g.replay() if mode == "graph" else R.render(cam, "fp16", "f16", rgba=rgba, split=False)
+            g.replay() if mode == "graph" else R.render(cam, "fp16", "f16", rgba=rgba)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(frames):
-            g.replay() if mode == "graph" else R.render(cam, "fp16", "f16", rgba=rgba, split=False)
+            g.replay() if mode == "graph" else R.render(cam, "fp16", "f16", rgba=rgba)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out[mode] = {"Mrays_per_s": round(frames * n / dt / 1e6, 1), "ms_per_frame": round(dt / frames * 1e3, 4)}
     torch.cuda.synchronize()
-    same = bool(torch.equal(g.replay(), R.render(cam, "fp16", "f16", split=False)))
+    same = bool(torch.equal(g.replay(), R.render(cam, "fp16", "f16")))
     torch.cuda.synchronize()
     out["replay_equals_eager"] = same
     log(f"graph: {out}")
@@ -415,6 +494,71 @@ def serve_bench(torch, P, R, duration_s, clients=32, rate_hz=30.0):
     return out
 
 
+def views_bench(torch, R, cams, frames_label):
+    """Frames over a list of cameras, FP16 path, one inrf_render each."""
+    r = run_frames(torch, R, cams, "fp16", "f16", len(cams), 3)
+    W, H = cams[0].width, cams[0].height
+    hits = sum(r["hits"]) / len(cams)
+    out = {"frames": len(cams), "width": W, "height": H, "protocol": frames_label,
+           "Mrays_per_s": round(W * H * len(cams) / r["wall_s"] / 1e6, 1),
+           "fps": round(len(cams) / r["wall_s"], 1),
+           "p50_ms": round(pct(r["frame_ms"], 50), 4), "p99_ms": round(pct(r["frame_ms"], 99), 4),
+           "hit_fraction": round(hits / (W * H), 4)}
+    log(f"{frames_label}: {out}")
+    return out
+
+
+def compulsory_bench(torch, P, R, cam):
+    """The gather's compulsory traffic on one 4K frame (FP16 tables): the
+    distinct 128-byte lines of the feature table and of the offset table
+    that the frame's hit rays touch, per level (each counted once, as if
+    every later touch hit in cache), against the bytes the rays request."""
+    import numpy as np
+    n = cam.width * cam.height
+    depth = torch.empty(n, device="cuda")
+    R.render(cam, "fp16", "f16", depth=depth)
+    o, d = P.camera_rays(cam)
+    hit = torch.isfinite(depth)
+    x = (o[hit] + depth[hit, None] * d[hit]).clamp(0.0, 1.0).contiguous()
+    _, slots = R.encode(x, table="f16", slots=True)
+    corners = torch.tensor([[c & 1, (c >> 1) & 1, (c >> 2) & 1] for c in range(8)], device="cuda")
+
+    def lines(side, cx, cy, cz):
+        # storage index of the brick layout (8 x 4 x 1 cells, inrf_brick_index), 32 four-byte entries per line
+        row = 32 * ((side + 7) // 8)
+        plane = row * ((side + 3) // 4)
+        idx = cz * plane + (cy // 4) * row + (cx // 8) * 32 + (cy % 4) * 8 + cx % 8
+        return int(torch.unique(idx // 32).numel())
+
+    table_lines = phi_lines = 0
+    for l, lv in enumerate(R.levels):
+        m, rb, N = lv.mbar, lv.rbar, lv.res
+        sl = slots[:, l, :].reshape(-1).long()
+        table_lines += lines(m, sl % m, (sl // m) % m, sl // (m * m))
+        p = torch.clamp(torch.floor(x * N), max=N - 1).long()
+        v = (p[:, None, :] + corners[None]).reshape(-1, 3) % rb
+        phi_lines += lines(rb, v[:, 0], v[:, 1], v[:, 2])
+    hits = int(hit.sum().item())
+    requested = hits * requested_bytes_per_hit(R.n_levels, "f16")
+    out = {"hit_rays": hits, "requested_bytes": requested, "table_lines": table_lines, "offset_lines": phi_lines,
+           "compulsory_bytes": 128 * (table_lines + phi_lines),
+           "compulsory_over_requested": round(128 * (table_lines + phi_lines) / requested, 4)}
+    log(f"compulsory: {out}")
+    del slots, x
+    return out
+
+
+def peaks_bench(torch):
+    """Measured ceilings (libinrf_peaks.so): streaming HBM read of a 4 GiB
+    buffer and the network's matrix instructions in FP32, FP16 and BF16."""
+    from paper_2303_04086_amd import peaks
+    out = {"hbm_read": peaks.hbm_read(torch)}
+    for prec in ("fp16", "bf16", "fp32"):
+        out["mfma_" + prec] = peaks.mfma(torch, prec)
+    log(f"peaks: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -424,13 +568,16 @@ def main():
                     help="camera distance from the object centre (the headline workload uses 2.0)")
     ap.add_argument("--width", type=int, default=3840)
     ap.add_argument("--height", type=int, default=2160)
-    ap.add_argument("--cpu-sample", type=int, default=4096)
+    ap.add_argument("--cpu-sample", type=int, default=8192,
+                    help="pixels of the oracle baseline (three quarters near the object)")
+    ap.add_argument("--cpu-one-core", type=int, default=1024, help="of which timed again on one core")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mlp", action="store_true")
-    ap.add_argument("--no-split", action="store_true",
-                    help="time unsplit frames only (profiling runs: every shading launch then covers a whole frame)")
     ap.add_argument("--mlp-rays", type=int, default=1 << 24)
     ap.add_argument("--sweep-frames", type=int, default=8, help="frames per sweep case (0: no sweep)")
+    ap.add_argument("--views", type=int, default=200,
+                    help="seeded random 4K views of the paper's average-over-views protocol (0: none)")
+    ap.add_argument("--no-peaks", dest="peaks", action="store_false", help="skip the measured-ceiling leg")
     ap.add_argument("--train-steps", type=int, default=10, help="timed training steps (0: none)")
     ap.add_argument("--train-batch", type=int, default=1 << 18)
     ap.add_argument("--scene-frames", type=int, default=16, help="timed frames of the 12-object scene (0: none)")
@@ -463,18 +610,25 @@ def main():
               "so a frame would shard by tiles with no exchange); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
-    import torch
     import synth
-    import paper_2303_04086_amd as P
-    if not torch.cuda.is_available():
-        print("no GPU visible", file=sys.stderr)
-        sys.exit(1)
 
     W, H = args.width, args.height
     w = synth.workload_object(W, H)
     if args.distance != 2.0:
         w.cameras = synth.fibonacci_cameras(8, args.distance, W, H)
         w.name += f"_d{args.distance}"
+    base = ref = None
+    if not args.no_cpu_baseline:
+        # on the host cores before anything touches the GPU (the workers are forked)
+        log(f"timing the FP64 oracle on {args.cpu_sample} rays ...")
+        base, ref = cpu_baseline(w, args.cpu_sample * 3 // 4, args.cpu_sample // 4, args.cpu_one_core)
+        log(f"oracle: {base}")
+
+    import torch
+    import paper_2303_04086_amd as P
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
     log(f"workload {w.name}: {len(w.tris)} triangles, levels {w.res}")
     t0 = time.time()
     levels = P.build_psh(w.verts, w.tris, w.res, dilate=w.dilate, seed=w.psh_seed)
@@ -487,15 +641,19 @@ def main():
     log(f"device model resident ({R.n_slots} slots/table) in {time.time() - t0:.1f} s")
 
     out = {}
-    for prec, table in (("fp16", "f16"), ("fp32", "f32")):
-        r = run_frames(torch, R, w.cameras, prec, table, args.steps, args.warmup, split=not args.no_split)
+    for prec, table in (("fp16", "f16"), ("fp32", "f32"), ("bf16", "f16")):
+        r = run_frames(torch, R, w.cameras, prec, table, args.steps, args.warmup)
         out[prec] = (r, summarize(r, W, H, args.steps, R.n_levels, table))
         log(f"{prec}: {out[prec][1]['value']} Mrays/s, p50 {out[prec][1]['p50_ms']} ms, "
             f"p99 {out[prec][1]['p99_ms']} ms, trace {out[prec][1]['trace_ms_avg']} ms, "
-            f"shade {out[prec][1]['shade_ms_avg']} ms; unsplit {out[prec][1]['unsplit_Mrays_per_s']} Mrays/s")
+            f"shade {out[prec][1]['shade_ms_avg']} ms")
+    errors = None
+    if ref is not None:
+        errors = frame_errors(torch, R, w.cameras[0], ref, (("fp32", "f32"), ("fp16", "f16"), ("bf16", "f16")))
+        log(f"errors against FP64: {errors}")
     mlp = {}
     if not args.no_mlp:
-        for prec in ("fp16", "fp32"):
+        for prec in ("fp16", "bf16", "fp32"):
             mlp[prec] = mlp_bench(torch, R, prec, args.mlp_rays)
             log(f"mlp {prec}: {mlp[prec]}")
     # two frames in flight, measured before the legs that create more streams: with more than four
@@ -504,6 +662,14 @@ def main():
              if args.pipelined_frames > 0 else None)
     graph = graph_bench(torch, P, R) if args.graph else None
     sweep = sweep_bench(torch, R, w, args.sweep_frames) if args.sweep_frames > 0 else None
+    views = None
+    if args.views > 0:
+        views = {"w2_200": views_bench(torch, R, synth.random_cameras(args.views, 21, 2.0, W, H),
+                                       f"{args.views} seeded random views at distance 2"),
+                 "w2_800": views_bench(torch, R, synth.fibonacci_cameras(8, 2.0, 800, 800) * 5,
+                                       "800x800, the 8 cameras 5 times")}
+    compulsory = compulsory_bench(torch, P, R, w.cameras[0])
+    peaks = peaks_bench(torch) if args.peaks else None
     scene = scene_bench(torch, P, args.scene_frames, W, H) if args.scene_frames > 0 else None
     serve = serve_bench(torch, P, R, args.serve_seconds) if args.serve_seconds > 0 else None
     nolf = nolf_bench(torch, P, args.nolf_frames, W, H) if args.nolf_frames > 0 else None
@@ -513,17 +679,43 @@ def main():
     if args.train_steps > 0:
         train = train_bench(torch, R, w, args.train_steps, args.train_batch)
         log(f"train: {train}")
-    base = None
-    if not args.no_cpu_baseline:
-        log(f"timing the FP64 oracle on {args.cpu_sample} rays ...")
-        base = cpu_baseline(w, args.cpu_sample)
-        log(f"oracle: {base['value']} Mrays/s")
 
     head = out["fp16"][1]
     r16 = out["fp16"][0]
     shade_avg_s = sum(r16["shade_ms"]) / args.steps / 1e3
     bytes_launch = sum(r16["hits"]) / args.steps * requested_bytes_per_hit(R.n_levels, "f16")
     achieved = bytes_launch / shade_avg_s / 1e9
+    traffic = load_traffic("k_shade_f16")
+    roof = {"kernel": "k_shade (PSH gather + trilinear + SH16 + MLP)", "bound": "hbm",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "per_unit": f"{requested_bytes_per_hit(R.n_levels, 'f16')} B requested per hit ray",
+            "units_per_launch": round(sum(r16["hits"]) / args.steps, 1),
+            "avg_launch_ms": round(shade_avg_s * 1e3, 4)}
+    if traffic:
+        roof["traffic_GBps"] = round(traffic / shade_avg_s / 1e9, 1)
+        roof["traffic_frac"] = round(traffic / shade_avg_s / 1e9 / HBM_PEAK_GBS, 4)
+    if peaks:
+        mp = peaks["hbm_read"]["GBps"]
+        roof["measured_peak"] = mp
+        roof["frac_of_measured_peak"] = round(achieved / mp, 4)
+        if traffic:
+            roof["traffic_frac_of_measured_peak"] = round(traffic / shade_avg_s / 1e9 / mp, 4)
+        for prec in mlp:
+            mlp[prec]["measured_peak"] = peaks["mfma_" + prec]["TFLOPs"]
+            mlp[prec]["utilisation_of_measured_peak"] = round(mlp[prec]["TFLOPs"] / peaks["mfma_" + prec]["TFLOPs"], 4)
+    ratio = round(head["value"] / out["fp32"][1]["value"], 3)
+    targets = {"gather_ge_0.60_of_hbm": {"value": roof["frac"], "met": bool(roof["frac"] >= 0.60)}}
+    if mlp:
+        targets["mlp_ge_0.40_of_mfma"] = {"value": mlp["fp16"]["utilisation"],
+                                          "met": bool(mlp["fp16"]["utilisation"] >= 0.40)}
+    if errors:
+        targets["fp32_max_abs_le_1e-5"] = {"value": errors["fp32"]["max_abs"],
+                                           "met": bool(errors["fp32"]["max_abs"] <= 1e-5)}
+        targets["fp16_max_abs_le_2e-3_psnr_ge_50"] = {
+            "value": [errors["fp16"]["max_abs"], errors["fp16"]["psnr_db"]],
+            "met": bool(errors["fp16"]["max_abs"] <= 2e-3 and (errors["fp16"]["psnr_db"] or 1e9) >= 50.0)}
+    targets["fp16_ge_2x_fp32"] = {"value": ratio, "met": bool(ratio >= 2.0)}
     line = {
         "metric": METRIC,
         "value": head["value"],
@@ -544,16 +736,16 @@ def main():
         "p99_ms": head["p99_ms"],
         "fp16": head,
         "fp32": out["fp32"][1],
-        "fp16_over_fp32": round(head["value"] / out["fp32"][1]["value"], 3),
-        "roofline": {"kernel": "k_shade (PSH gather + trilinear + SH16 + MLP)", "bound": "hbm",
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": load_traffic("k_shade_f16"),
-                     "per_unit": f"{requested_bytes_per_hit(R.n_levels, 'f16')} B requested per hit ray",
-                     "units_per_launch": round(sum(r16["hits"]) / args.steps, 1),
-                     "avg_launch_ms": round(shade_avg_s * 1e3, 4)},
+        "bf16": out["bf16"][1],
+        "fp16_over_fp32": ratio,
+        "errors_vs_fp64": errors,
+        "targets": targets,
+        "roofline": roof,
+        "peaks": peaks,
+        "compulsory": compulsory,
         "mlp": mlp or None,
         "sweep": sweep,
+        "views": views,
         "scene": scene,
         "single_level": single,
         "serve": serve,

@@ -239,17 +239,13 @@ int64_t inrf_workspace_size(int64_t n_rays);
  * [height*width], distance along the unit ray, +inf on a miss) and tri
  * (device int32 [height*width], proxy triangle index, -1 on a miss).
  * ws: device workspace of at least inrf_workspace_size(width*height) bytes;
- * its first two int32 receive the frame's hit-ray count (the sum of both).
- * A frame of more than 112 pixel rows (8 tile rows of 16) is rendered as
- * two halves of tile rows: the top on `stream`, the bottom on a second
- * stream owned by the library, forked from and joined back into `stream`
- * with two events, so the trace of one half can run beside the shading of
- * the other.  The library creates that stream and its two events on the
- * first split frame of each (device, caller stream) pair and keeps them
- * until the process ends (default priority, non-blocking); split frames
- * issued concurrently from several host threads on one caller stream must
- * be serialised by the caller.  The pixels are exactly those of an unsplit
- * frame (inrf_render_profiled and inrf_render_batch never split). */
+ * its first two int32 receive the frame's hit-ray count and zero.  The
+ * proxy's triangles are first sorted into lists per 8x8-pixel quadrant of
+ * the frame (the workspace holds up to width*height list entries; a
+ * quadrant whose list does not fit is traced through the BVH instead), and
+ * every ray is tested against its quadrant's list: the closest hit (ties to
+ * the lower triangle index) is the one inrf_forward finds on the same ray
+ * through the BVH.  Everything is enqueued on `stream`. */
 inrf_status inrf_render(const inrf_model* m, int32_t precision, const inrf_camera* cam, float* rgba,
                         float* depth, int32_t* tri, void* ws, int64_t ws_bytes, void* stream);
 
@@ -274,8 +270,8 @@ inrf_status inrf_render_profiled(const inrf_model* m, int32_t precision, const i
  * device array of the library (74.5 MiB, held by each GPU the library
  * runs on until the process ends), so frames are limited to
  * INRF_STATIC_MAX_PIXELS pixels (INRF_E_SIZE beyond, nothing enqueued).
- * The call allocates nothing and creates no runtime object; the frame is
- * never split in halves.  Every call on one GPU shares that array: calls
+ * The call allocates nothing and creates no runtime object.  Every call on
+ * one GPU shares that array: calls
  * that may overlap on one GPU (different streams without ordering between
  * them, or several host threads) race and must be serialised by the
  * caller.  Nothing in the array needs to start at zero: every value a

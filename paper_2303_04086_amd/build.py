@@ -15,6 +15,8 @@ LIB = os.path.join(HERE, "libinrf.so")
 ARCH = "gfx950"
 
 SOURCES = ["psh.cpp", "voxel.cpp", "bvh.cpp", "render.hip", "optim.hip"]
+PEAK_SOURCES = ["peaks.hip"]
+PEAKS_LIB = os.path.join(HERE, "libinrf_peaks.so")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", f"-I{INCLUDE}", f"-I{CSRC}"]
 # every HIP translation unit: gfx950 only, no packed FP32 instructions
 HIP_FLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -40,18 +42,25 @@ def _compile(src: str) -> str:
     return out
 
 
-def build(verbose: bool = True) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+def _link(objs, lib):
+    tmp = lib + ".tmp"
     cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"linking failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = True) -> str:
+    """libinrf.so (the render path) and libinrf_peaks.so (the benchmark's
+    measurement kernels, include/inrf_peaks.h)."""
+    os.makedirs(BUILD, exist_ok=True)
+    with ThreadPoolExecutor(len(SOURCES) + len(PEAK_SOURCES)) as ex:
+        objs = list(ex.map(_compile, SOURCES + PEAK_SOURCES))
+    _link(objs[:len(SOURCES)], LIB)
+    _link(objs[len(SOURCES):], PEAKS_LIB)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {PEAKS_LIB}")
     return LIB
 
 

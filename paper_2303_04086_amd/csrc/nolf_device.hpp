@@ -142,7 +142,8 @@ __global__ void k_cube_macro(const int32_t* __restrict__ index, int b, uint8_t* 
 __global__ __launch_bounds__(kThreads) void k_march(CubesC C, CamC cam, MarchArgs a) {
     __shared__ int s_cnt[kThreads / 64];
     const int lane = __lane_id(), wave = int(threadIdx.x) / 64;
-    const int tx = int(blockIdx.x) % cam.tiles_x, ty = int(blockIdx.x) / cam.tiles_x;
+    int tx, ty;
+    tile_at(int(blockIdx.x), cam.tiles_x, (cam.H + kTile - 1) / kTile, tx, ty);
     const int row = ty * kTile + 8 * (wave >> 1) + (lane >> 3), col = tx * kTile + 8 * (wave & 1) + (lane & 7);
     const bool valid = row < cam.H && col < cam.W;
     const int64_t ray = int64_t(row) * cam.W + col;

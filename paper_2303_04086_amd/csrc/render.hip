@@ -1,12 +1,17 @@
 // Device entry points of libinrf: closest-hit trace, position encoding, the
 // network alone, and the fused per-ray path (inrf_render / inrf_forward).
 //
-// A frame is five launches on the caller's stream:
-//   k_trace   one ray per lane: generate (camera) or load (batch) the ray,
-//             closest hit through the BVH with a watertight triangle test
-//             (a camera wave traverses as one packet), write depth / triangle
-//             / zero colour for misses, and write the hit records (hit point,
-//             unit direction, output index) of each tile in lane order;
+// A camera frame is ten launches on the caller's stream:
+//   k_bin_clear, k_bin (count), k_scan_local, k_scan_runs, k_bin (fill)
+//             sort the proxy's triangles into lists per 8x8-pixel quadrant
+//             of the frame (bin_device.hpp);
+//   k_trace   one ray per lane, tiles in strip order: generate (camera) or
+//             load (batch) the ray, closest hit with a watertight triangle
+//             test against the wave's quadrant list (camera; the BVH where a
+//             list is missing) or through the BVH (batch), write depth /
+//             triangle / zero colour for misses, and write the hit records
+//             (hit point, unit direction, output index) of each tile in lane
+//             order;
 //   k_scan_local, k_scan_runs, k_compact  pack the records into one list in
 //             tile order (deterministic) and count them;
 //   k_shade   persistent waves over the packed hits: multi-level PSH gather
@@ -54,6 +59,22 @@ struct CamC {
     int32_t tile0;       // first tile of this camera in a batch of cameras
     int64_t pix0;        // first output pixel of this camera in a batch
 };
+
+// Order in which a frame's tiles are traced, and so in which their hits are
+// packed and shaded: strips of kStrip tile rows, each strip column after
+// column (top to bottom inside a column).  Rays in flight together then
+// cover a compact patch of the image rather than a band of whole rows, so
+// the corners that neighbouring tiles share (above and below as well as
+// left and right) are read while they are still cached.
+constexpr int kStrip = 8;
+
+__host__ __device__ __forceinline__ void tile_at(int t, int tiles_x, int tiles_y, int& tx, int& ty) {
+    const int strip = t / (kStrip * tiles_x);
+    const int rows = min(kStrip, tiles_y - strip * kStrip);
+    const int r = t - strip * kStrip * tiles_x;
+    tx = r / rows;
+    ty = strip * kStrip + r % rows;
+}
 
 // Unit direction of the ray through the centre of pixel (row, col):
 // normalize(f + s_x r + s_y u) with s_x = (2(col + 1/2)/W - 1) tan_x and
@@ -376,7 +397,9 @@ __global__ __launch_bounds__(kThreads) void k_trace(ModelC m, CamSet<NCAM> cams,
         for (int k = 1; k < NCAM && k < cams.n; ++k)
             if (int(blockIdx.x) >= cams.c[k].tile0) j = k;
         const CamC& cam = cams.c[j];
-        const int tile = int(blockIdx.x) - cam.tile0, tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+        const int tile = int(blockIdx.x) - cam.tile0;
+        int tx, ty;
+        tile_at(tile, cam.tiles_x, (cam.H + kTile - 1) / kTile, tx, ty);
         const int row = ty * kTile + 8 * (wave >> 1) + (lane >> 3), col = tx * kTile + 8 * (wave & 1) + (lane & 7);
         qx = 2 * tx + (wave & 1);
         qy = 2 * ty + (wave >> 1);
@@ -507,7 +530,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_runs(int32_t* __restrict_
         __syncthreads();
     }
     if (threadIdx.x == 0) *counter = carry;
-    if (int(threadIdx.x) < n_clear) clear[threadIdx.x] = 0;  // the other chunks' counts of an unsplit frame
+    if (int(threadIdx.x) < n_clear) clear[threadIdx.x] = 0;  // the header's other counters
 }
 
 // Packs the workgroups' records into one list in workgroup order (tile
@@ -763,7 +786,7 @@ namespace {
 using namespace dev;
 
 constexpr int64_t kWsHeader = 256;
-constexpr int kMaxChunks = 2;  // hit counters of a split frame's halves at the start of the header
+constexpr int kMaxChunks = 2;  // hit counters at the start of the header: the frame's, then one kept at zero
 
 constexpr int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
 
@@ -1116,95 +1139,10 @@ void trace_to_hits(const ModelC& c, const CamSet<NCAM>* cams, const float* ray_o
     launch_check("k_compact");
 }
 
-// The second stream of a split frame with its fork and join events: one set
-// per (device, caller stream), default priority, non-blocking, created on
-// first use and kept until the process ends, so a frame creates no runtime
-// objects.  Frames split from different caller streams never wait on each
-// other; frames split from one caller stream are ordered by that stream.
-struct AuxStream {
-    int dev;
-    hipStream_t caller, s2;
-    hipEvent_t fork, join;
-};
-
-AuxStream aux_stream(hipStream_t caller) {
-    static std::mutex mu;
-    static std::vector<AuxStream> streams;
-    int dev = 0;
-    check_hip(hipGetDevice(&dev), "hipGetDevice");
-    std::lock_guard<std::mutex> lock(mu);
-    for (const auto& e : streams)
-        if (e.dev == dev && e.caller == caller) return e;
-    AuxStream a{dev, caller, nullptr, nullptr, nullptr};
-    check_hip(hipStreamCreateWithFlags(&a.s2, hipStreamNonBlocking), "hipStreamCreate");
-    check_hip(hipEventCreateWithFlags(&a.fork, hipEventDisableTiming), "hipEventCreate");
-    check_hip(hipEventCreateWithFlags(&a.join, hipEventDisableTiming), "hipEventCreate");
-    streams.push_back(a);
-    return a;
-}
-
-// Trace, pack and shade camera tiles [t0, t1) of one camera on stream s:
-// records of the range go to recs, its hit count to *counter.  The ranges'
-// per-tile entries, scan runs and records occupy disjoint parts of the
-// workspace arrays.
-template <class TableT>
-void camera_range(const ModelC& c, int32_t precision, const CamSet<1>& cams, int t0, int t1, float* rgba,
-                  float* depth, int32_t* tri, HitRec* tmp, int2* blk, int32_t* offsets, int32_t* runs, HitRec* recs,
-                  int32_t* counter, hipStream_t s, const BinsC* bins) {
-    CamSet<1> cs = cams;
-    cs.c[0].tile0 = -t0;  // workgroup b traces tile t0 + b
-    const int n_blk = t1 - t0;
-    const TraceArgs a{nullptr, nullptr, 0, rgba, depth, tri, tmp, blk + t0};
-    launch_trace(c, &cs, a, 0, s, bins);
-    const int n_runs = (n_blk + kScanRun - 1) / kScanRun;
-    hipLaunchKernelGGL(k_scan_local, dim3(n_runs), dim3(kScanThreads), 0, s, reinterpret_cast<const int32_t*>(blk + t0), 2, n_blk, offsets + t0, runs, INT32_MAX);
-    launch_check("k_scan_local");
-    hipLaunchKernelGGL(k_scan_runs, dim3(1), dim3(kScanThreads), 0, s, runs, n_runs, counter, nullptr, 0);
-    launch_check("k_scan_runs");
-    hipLaunchKernelGGL(k_compact, dim3(n_blk), dim3(kThreads), 0, s, blk + t0, offsets + t0, runs, tmp, recs);
-    launch_check("k_compact");
-    launch_shade<TableT>(c, precision, recs, nullptr, counter, rgba, s);
-    launch_check("k_shade");
-}
-
-// A camera frame in two halves of tile rows: the top half on the caller's
-// stream, the bottom half on its second stream, forked and joined with
-// events.  Where one half's trace (bound by ALU issue) and the other's
-// shading (bound by HBM gathers) meet, they run side by side.  Every pixel
-// is computed exactly as in the unsplit frame.  Header: hit counts of the
-// two halves at int32 0 and 1.
-template <class TableT>
-void run_split(const ModelC& c, int32_t precision, const CamSet<1>& cams, float* rgba, float* depth, int32_t* tri,
-               void* ws, const WsLayout& L, hipStream_t s, const BinsC* bins) {
-    const CamC& cam = cams.c[0];
-    const int tiles_y = (cam.H + kTile - 1) / kTile, n_tiles = cam.tiles_x * tiles_y;
-    const int tA = (tiles_y / 2) * cam.tiles_x;
-    const int64_t nA = int64_t(tiles_y / 2) * kTile * cam.W;  // pixels of the top half
-    int32_t* counter = ws_at<int32_t>(ws, 0);
-    HitRec* recs = ws_at<HitRec>(ws, L.recs);
-    HitRec* tmp = ws_at<HitRec>(ws, L.tmp);
-    int2* blk = ws_at<int2>(ws, L.blk);
-    int32_t* offsets = ws_at<int32_t>(ws, L.offsets);
-    int32_t* runs = ws_at<int32_t>(ws, L.runs);
-    const int runsA = (tA + kScanRun - 1) / kScanRun;
-    const AuxStream aux = aux_stream(s);
-    hipStream_t s2 = aux.s2;
-    check_hip(hipEventRecord(aux.fork, s), "hipEventRecord");
-    check_hip(hipStreamWaitEvent(s2, aux.fork, 0), "hipStreamWaitEvent");
-    camera_range<TableT>(c, precision, cams, 0, tA, rgba, depth, tri, tmp, blk, offsets, runs, recs, counter, s, bins);
-    camera_range<TableT>(c, precision, cams, tA, n_tiles, rgba, depth, tri, tmp, blk, offsets, runs + runsA,
-                         recs + nA, counter + 1, s2, bins);
-    check_hip(hipEventRecord(aux.join, s2), "hipEventRecord");
-    check_hip(hipStreamWaitEvent(s, aux.join, 0), "hipStreamWaitEvent");
-}
-
-// Frames of at least this many tile rows are split in two.
-constexpr int kSplitTileRows = 8;
-
 template <int NCAM>
 void run_path(const inrf_model* m, int32_t precision, const CamSet<NCAM>* cams, const float* ray_o,
               const float* ray_d, int64_t n, float* rgba, float* depth, int32_t* tri, void* ws, int64_t ws_bytes,
-              void* stream, void* const* events = nullptr, bool split = false) {
+              void* stream, void* const* events = nullptr) {
     check_precision(precision);
     const ModelC c = make_model(m, true, true);
     require(m->weights != nullptr, "weights must be set");
@@ -1226,13 +1164,6 @@ void run_path(const inrf_model* m, int32_t precision, const CamSet<NCAM>* cams, 
     }
     record(events, 0, s);
     if (bins) bin_frame(c, *bins, s);
-    if constexpr (NCAM == 1) {
-        if (split && cams && !events && (cams->c[0].H + kTile - 1) / kTile >= kSplitTileRows) {
-            if (c.table_dtype == INRF_F32) run_split<float>(c, precision, *cams, rgba, depth, tri, ws, L, s, bins);
-            else run_split<__half>(c, precision, *cams, rgba, depth, tri, ws, L, s, bins);
-            return;
-        }
-    }
     const int32_t* counter = ws_at<int32_t>(ws, 0);
     const HitRec* recs = ws_at<HitRec>(ws, L.recs);
     trace_to_hits(c, cams, ray_o, ray_d, n, rgba, depth, tri, ws, s, bins);
@@ -1632,7 +1563,7 @@ inrf_status inrf_render(const inrf_model* m, int32_t precision, const inrf_camer
     return guarded("inrf_render", [&] {
         const dev::CamSet<1> cs{1, 0, {make_camera(cam)}};
         run_path(m, precision, &cs, nullptr, nullptr, int64_t(cs.c[0].W) * cs.c[0].H, rgba, depth, tri, ws, ws_bytes,
-                 stream, nullptr, true);
+                 stream);
     });
 }
 
@@ -1644,9 +1575,8 @@ inrf_status inrf_render_static(const inrf_model* m, int32_t precision, const inr
         if (n > INRF_STATIC_MAX_PIXELS)
             fail(INRF_E_SIZE, "inrf_render_static renders at most " + std::to_string(INRF_STATIC_MAX_PIXELS) +
                                   " pixels, got " + std::to_string(n));
-        // unsplit: a split frame would need the library's second stream
         run_path(m, precision, &cs, nullptr, nullptr, n, rgba, depth, tri, static_scratch(), kStaticScratchBytes,
-                 stream, nullptr, false);
+                 stream);
     });
 }
 

@@ -55,7 +55,9 @@ __global__ __launch_bounds__(kThreads) void k_trace_scene(SceneC sc, CamC cam, S
     __shared__ int wst[(kThreads / 64) * kBvhMaxStack];
     __shared__ int s_cnt[kThreads / 64][kMaxObjects];
     const int lane = __lane_id(), wave = int(threadIdx.x) / 64;
-    const int b = blockIdx.x, tx = b % cam.tiles_x, ty = b / cam.tiles_x;
+    const int b = blockIdx.x;
+    int tx, ty;
+    tile_at(b, cam.tiles_x, (cam.H + kTile - 1) / kTile, tx, ty);
     const int row = ty * kTile + 8 * (wave >> 1) + (lane >> 3), col = tx * kTile + 8 * (wave & 1) + (lane & 7);
     const bool valid = row < cam.H && col < cam.W;
     const int64_t ray = int64_t(row) * cam.W + col;

@@ -244,15 +244,12 @@ class Renderer:
 
     # -- calls -------------------------------------------------------------
     def render(self, cam, precision="fp32", table="f32", rgba=None, depth=None, tri=None, stream=None,
-               events=None, ws=None, split=True):
+               events=None, ws=None):
         """Render one camera.  `events`: optional three recorded
         torch.cuda.Event objects marking trace start, shading start and end
-        (the frame is then not split).  `ws`: optional uint8 workspace of the
+        (inrf_render_profiled).  `ws`: optional uint8 workspace of the
         caller (frames in flight on different streams need one each); else
-        the renderer's own.  `split=False`: never render the frame as two
-        halves on two streams (e.g. when frames already overlap)."""
-        if events is None and not split:
-            events = (None, None, None)   # the stage-event entry point never splits
+        the renderer's own."""
         torch = self.torch
         n = int(cam.width) * int(cam.height)
         if rgba is None:
@@ -300,8 +297,7 @@ class Renderer:
 
     def hit_count(self) -> int:
         """Hit rays of the last render/forward (reads the workspace header:
-        the hit counts of a frame's two halves, the second zero when the
-        frame was not split)."""
+        the frame's hit count, then a counter kept at zero)."""
         return int(self._ws[:8].view(self.torch.int32).sum().item())
 
     def forward(self, o, d, precision="fp32", table="f32", depth=None, tri=None, rgba=None, stream=None):
@@ -494,7 +490,7 @@ class NolfRenderer:
 
 class CapturedFrame:
     """One camera frame captured as a HIP graph (torch.cuda.CUDAGraph) and
-    replayed: the five launches of an unsplit render of a fixed camera into
+    replayed: the launches of a render of a fixed camera into
     fixed buffers with a workspace of its own, enqueued with one call.  The
     path records no memset (counters are written by kernels), so a replay
     recomputes the frame exactly as the eager render does."""
@@ -509,7 +505,7 @@ class CapturedFrame:
         self.tri = torch.empty(n, dtype=torch.int32, device=dev) if tri else None
         self.ws = torch.empty(int(L.lib().inrf_workspace_size(n)), dtype=torch.uint8, device=dev)
         args = (cam, precision, table)
-        kw = dict(rgba=self.rgba, depth=self.depth, tri=self.tri, ws=self.ws, split=False)
+        kw = dict(rgba=self.rgba, depth=self.depth, tri=self.tri, ws=self.ws)
         side = torch.cuda.Stream(device=dev)
         side.wait_stream(torch.cuda.current_stream(dev))
         with torch.cuda.stream(side):   # warm-up: kernel attributes and occupancy queries happen here
@@ -562,8 +558,7 @@ class FramePipeline:
         for t in (rgba, depth, tri):
             if t is not None:
                 t.record_stream(s)
-        # frames already overlap each other here: no split in halves
-        self.R.render(cam, precision, table, rgba=rgba, depth=depth, tri=tri, stream=s, ws=ws, split=False)
+        self.R.render(cam, precision, table, rgba=rgba, depth=depth, tri=tri, stream=s, ws=ws)
         ev = torch.cuda.Event()
         ev.record(s)
         self.events[slot] = ev

@@ -196,8 +196,7 @@ def _cam(W, H, direction=(0.3, -0.8, 0.52)):
 def test_render_is_deterministic_and_equals_forward(tiny, R, wh):
     """Two renders of a frame are identical, and equal inrf_forward on the
     camera's own rays (inrf_camera_rays) bit for bit: colour, depth and
-    triangle, in every precision.  200 x 150 has 10 tile rows, so the render
-    is split in two halves on two streams."""
+    triangle, in every precision."""
     import paper_2303_04086_amd as P
     cam = tiny.cameras[0] if wh == (64, 64) else _cam(*wh)
     n = cam.width * cam.height

@@ -1,8 +1,7 @@
-"""A camera frame of 8 or more tile rows renders as two halves of tile rows
-on two streams (inrf_render); the stage-event entry point
-(inrf_render_profiled) never splits.  Both must give the same pixels,
-depth, triangle ids and hit count bit for bit: the halves trace, pack and
-shade exactly the rays of the unsplit frame."""
+"""inrf_render and the stage-event entry point inrf_render_profiled must
+give the same pixels, depth, triangle ids and hit count bit for bit, at
+ragged sizes whose tile strips end part way, and frames of different sizes
+issued back to back on one stream must each equal a lone render."""
 import numpy as np
 import pytest
 
@@ -33,7 +32,7 @@ def _frame(R, cam, prec, table, profiled):
 
 @pytest.mark.parametrize("wh", [(160, 300), (64, 520), (257, 450), (100, 1100)])
 @pytest.mark.parametrize("prec,table", [("fp32", "f32"), ("fp16", "f16")])
-def test_split_frame_equals_unsplit(R, wh, prec, table):
+def test_render_equals_profiled(R, wh, prec, table):
     cam = synth.look_at_camera(np.array([0.5, 0.5, 0.5]) + 1.6 * np.array([0.3, -0.8, 0.52]), (0.5, 0.5, 0.5),
                                40.0, *wh)
     a = _frame(R, cam, prec, table, profiled=False)
@@ -42,9 +41,9 @@ def test_split_frame_equals_unsplit(R, wh, prec, table):
     assert a[3] == b[3] == int((b[2] >= 0).sum().item()) > 0
 
 
-def test_split_frames_back_to_back_on_one_stream(R):
-    """Frames of different sizes in a row, split and unsplit interleaved,
-    without synchronisation in between: each equals its lone render."""
+def test_frames_back_to_back_on_one_stream(R):
+    """Frames of different sizes in a row without synchronisation in
+    between: each equals its lone render."""
     cams = [synth.look_at_camera(np.array([0.5, 0.5, 0.5]) + 2.0 * d, (0.5, 0.5, 0.5), 40.0, w, h)
             for d, (w, h) in zip(synth.camera.fibonacci_directions(4), [(200, 300), (64, 32), (130, 520), (96, 96)])]
     outs = [R.render(c, "fp16", "f16") for c in cams]

@@ -26,6 +26,21 @@ def test_library_exports_every_declared_symbol():
     assert lib.inrf_version() >= 100
 
 
+def test_peaks_library_exports_every_declared_symbol():
+    """The benchmark's measurement kernels (include/inrf_peaks.h) load and
+    refuse bad arguments on the host, before touching a device."""
+    from paper_2303_04086_amd import peaks
+    hdr = open(os.path.join(ROOT, "include", "inrf_peaks.h")).read()
+    declared = set(re.findall(r"\b(inrf_[a-z_]+)\s*\(", hdr))
+    lib = peaks.lib()
+    assert declared == set(peaks.EXPORTED)
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert lib.inrf_peak_read_sink_size() >= 256
+    assert lib.inrf_peak_hbm_read(None, 16, 1, None, None) == -1
+    assert lib.inrf_peak_mfma(7, 2, 10, 256, None) == -1 and b"precision" in lib.inrf_peaks_last_error()
+
+
 # Entry points that carry out a step of the paper's method: each one's
 # comment block in the header cites the passage that defines it.
 CITED = ["inrf_build_psh", "inrf_build_bvh", "inrf_render", "inrf_camera_rays", "inrf_forward", "inrf_render_batch",
