@@ -315,6 +315,15 @@ inrf_status inrf_encode(const inrf_model* m, const float* x, int64_t n, float* e
 inrf_status inrf_mlp(const inrf_model* m, int32_t precision, const float* in, int64_t n, float* rgba,
                      void* stream);
 
+/* The network on 16-bit inputs (Sec. 4.2, Eq. 3): enc device [n][2L]
+ * encodings of the precision's 16-bit type (INRF_PREC_FP16: IEEE half,
+ * INRF_PREC_BF16: bfloat16), dir device float32 [n][3] view directions
+ * (need not be unit); the SH16 values of dir / |dir| are computed on the
+ * fly, as the shading kernel does.  rgba device float32 [n][4], 16-byte
+ * aligned.  INRF_PREC_FP32 is refused (INRF_E_INVALID): use inrf_mlp. */
+inrf_status inrf_mlp_encoded(const inrf_model* m, int32_t precision, const void* enc, const float* dir, int64_t n,
+                             float* rgba, void* stream);
+
 /* ------------------------------------------------------------------------
  * Scenes of several objects (the paper composes objects per pixel by depth,
  * Sec. 5; scenes of several objects, Sec. 7).

@@ -16,8 +16,16 @@ barycentric coordinate within `eps_bary` of zero, or is met at a grazing
 angle, or the two nearest hits are within a relative `eps_t` in t.  All
 other rays have one correct answer.
 
+The cosine of the angle between each hit ray and the normal of the
+triangle it hits is returned beside the hit (`cos`, NaN for a miss).  Near
+grazing incidence the hit point moves by about t * (direction error) / cos
+for a small change of the direction, so an FP32 ray determines it only to
+~t * 2^-23 / |cos|; colour parity of the FP32 path is held where |cos| is
+not small (the tests' reading), and reported elsewhere.
+
 Pins: a ray aimed at a triangle's centroid along its normal hits that
-triangle at the closed-form plane distance; an empty proxy gives misses.
+triangle at the closed-form plane distance, with cos = 1; a ray at a known
+angle to the normal gives that angle's cosine; an empty proxy gives misses.
 """
 from __future__ import annotations
 
@@ -31,6 +39,7 @@ class HitResult:
     tri: np.ndarray        # int64 [n], -1 = miss
     t: np.ndarray          # float64 [n], +inf = miss
     ambiguous: np.ndarray  # bool [n]
+    cos: np.ndarray = None  # float64 [n]: |cos| of the incidence angle at the hit, NaN = miss
 
     @property
     def hit(self):
@@ -45,9 +54,10 @@ def closest_hit(o, d, verts, tris, eps_bary: float = 2.0 ** -16, eps_t: float = 
     tri_out = np.full(n, -1, np.int64)
     t_out = np.full(n, np.inf)
     amb = np.zeros(n, bool)
+    cos_out = np.full(n, np.nan)
     tris = np.asarray(tris, np.int64).reshape(-1, 3)
     if n == 0 or len(tris) == 0:
-        return HitResult(tri_out, t_out, amb)
+        return HitResult(tri_out, t_out, amb, cos_out)
     V = np.asarray(verts, np.float64)
     a = V[tris[:, 0]]
     e1 = V[tris[:, 1]] - a
@@ -82,6 +92,7 @@ def closest_hit(o, d, verts, tris, eps_bary: float = 2.0 ** -16, eps_t: float = 
         # ambiguity
         dn = np.linalg.norm(d[idx], axis=1)[:, None]
         cosang = np.abs(det) / (nrm[None] * dn)
+        cos_out[idx] = np.where(got, cosang[rows, best], np.nan)
         front = nz & (t > 0)
         near_edge = front & (np.abs(m) < eps_bary)
         grazing = (cosang < 1e-6) & (m > -eps_bary) & (t > 0)
@@ -91,4 +102,4 @@ def closest_hit(o, d, verts, tris, eps_bary: float = 2.0 ** -16, eps_t: float = 
         gap = np.where(got & np.isfinite(second), second - np.where(got, tbest, 0.0), np.inf)
         close_t = gap <= eps_t * np.abs(np.where(got, tbest, 0.0))
         amb[idx] = near_edge.any(axis=1) | grazing.any(axis=1) | close_t
-    return HitResult(tri_out, t_out, amb)
+    return HitResult(tri_out, t_out, amb, cos_out)

@@ -80,7 +80,8 @@ def render_rays(model: Model, o, d, **hit_kw) -> dict:
         enc[idx] = e
         inp = np.concatenate([e, sh_real(d[idx], model.sh_degree)], axis=1)
         rgba[idx] = mlp_forward(inp, model.weights)
-    return {"rgba": rgba, "tri": hit.tri, "t": hit.t, "x": x, "enc": enc, "ambiguous": hit.ambiguous}
+    return {"rgba": rgba, "tri": hit.tri, "t": hit.t, "x": x, "enc": enc, "ambiguous": hit.ambiguous,
+            "cos": hit.cos}
 
 
 def render_camera(model: Model, cam, rows=None, cols=None, **hit_kw) -> dict:

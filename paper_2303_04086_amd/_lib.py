@@ -25,7 +25,7 @@ EXPORTED = [
     "inrf_forward", "inrf_trace",
     "inrf_encode", "inrf_mlp", "inrf_batch_workspace_size", "inrf_render_batch", "inrf_scene_workspace_size", "inrf_render_scene", "inrf_backward_workspace_size",
     "inrf_backward", "inrf_adam", "inrf_render_nolf", "inrf_shade_nolf", "inrf_camera_rays",
-    "inrf_render_static",
+    "inrf_render_static", "inrf_mlp_encoded",
 ]
 
 
@@ -132,6 +132,7 @@ def _declare(lib):
         "inrf_camera_rays": (S, [POINTER(CameraDesc), c_void_p, c_void_p, c_void_p]),
         "inrf_render_static": (S, [POINTER(ModelDesc), c_int32, POINTER(CameraDesc), c_void_p, c_void_p, c_void_p,
                                    c_void_p]),
+        "inrf_mlp_encoded": (S, [POINTER(ModelDesc), c_int32, c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -196,27 +196,42 @@ __device__ __forceinline__ void load_inputs(const void* tile_row, float dx, floa
     }
 }
 
+// This lane's A operand of weight fragment f, from the LDS image (WLds) or
+// from registers the lane loaded it into once (WReg).
+template <class Vec>
+struct WLds {
+    const Vec* __restrict__ W;
+    int lane;
+    __device__ Vec operator()(int f) const { return W[f * 64 + lane]; }
+};
+template <class Vec, int N>
+struct WReg {
+    Vec w[N];
+    __device__ Vec operator()(int f) const { return w[f]; }
+};
+
 // The network for this lane's block of 16 rays given its first-layer B
 // operands.  Returns D of the output tile: for lanes l < 16, element i is
 // pre-sigmoid output i of ray l.
 template <class P, int F, int X = 0>
 __device__ __forceinline__ f32x4 mlp_block(const typename Mfma<P>::vec* __restrict__ W,
-                                           const typename Mfma<P>::vec* b1) {
+                                           const typename Mfma<P>::vec* b1);
+
+template <class P, int F, int X, class WA>
+__device__ __forceinline__ f32x4 mlp_block_w(const WA& wa, const typename Mfma<P>::vec* b1) {
     typedef Mfma<P> M;
     typedef typename M::vec Vec;
     constexpr int V = M::V, S1 = l1_steps(F, V, X), SH = hid_steps(V);
-    const int lane = __lane_id();
     f32x4 h1[4];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) h1[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < S1; ++s) {
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) h1[mt] = M::op(W[(mt * S1 + s) * 64 + lane], b1[s], h1[mt]);
+        for (int mt = 0; mt < 4; ++mt) h1[mt] = M::op(wa(mt * S1 + s), b1[s], h1[mt]);
         __builtin_amdgcn_sched_barrier(0);  // keep weight loads next to their use
     }
-    const Vec* W2 = W + 64 * 4 * S1;
-    const Vec* W3 = W2 + 64 * 4 * SH;
+    constexpr int F2 = 4 * S1, F3 = F2 + 4 * SH;  // first fragments of W2 and W3
     Vec b2[SH];
 #pragma unroll
     for (int s = 0; s < SH; ++s) {
@@ -236,7 +251,7 @@ __device__ __forceinline__ f32x4 mlp_block(const typename Mfma<P>::vec* __restri
         h2[ot] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < SH; ++s) {
-            h2[ot] = M::op(W2[(ot * SH + s) * 64 + lane], b2[s], h2[ot]);
+            h2[ot] = M::op(wa(F2 + ot * SH + s), b2[s], h2[ot]);
             if ((s & 3) == 3) __builtin_amdgcn_sched_barrier(0);
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -257,10 +272,22 @@ __device__ __forceinline__ f32x4 mlp_block(const typename Mfma<P>::vec* __restri
     f32x4 o = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < SH; ++s) {
-        o = M::op(W3[s * 64 + lane], b3[s], o);
+        o = M::op(wa(F3 + s), b3[s], o);
         if ((s & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
     return o;
+}
+
+template <class P, int F, int X>
+__device__ __forceinline__ f32x4 mlp_block(const typename Mfma<P>::vec* __restrict__ W,
+                                           const typename Mfma<P>::vec* b1) {
+    return mlp_block_w<P, F, X>(WLds<typename Mfma<P>::vec>{W, int(__lane_id())}, b1);
+}
+
+// Fragments of the whole weight image (first layer, then W2, then W3).
+template <class P, int F, int X = 0>
+__host__ __device__ constexpr int weight_frags() {
+    return 4 * l1_steps(F, Mfma<P>::V, X) + 5 * hid_steps(Mfma<P>::V);
 }
 
 }  // namespace dev

@@ -771,6 +771,98 @@ __global__ __launch_bounds__(kThreads) void k_mlp(ModelC m, const float* __restr
     }
 }
 
+// The network on 16-bit encodings and view directions: enc [n][2L] of the
+// precision's 16-bit type (P), dir [n][3] FP32.  Lane (g, r) loads exactly
+// its B operands of ray r (feature slots 32c + 8g .. +7 of the row, one
+// 16-byte load per chunk when `vec` says rows are 16-byte aligned) and
+// computes the SH values of the unit direction itself, as the shading
+// kernel does, so the input is 4L + 12 bytes per ray instead of
+// 4 (2L + 16).
+// Inputs of ray `ray` for lane group g: the chunks of its 16-bit encoding
+// row this lane supplies, and the view direction.
+template <class P, int F>
+struct EncIn {
+    typename Mfma<P>::vec e[F / 32];
+    float dx, dy, dz;
+};
+
+template <class P, int F>
+__device__ __forceinline__ EncIn<P, F> load_enc(const P* __restrict__ enc, const float* __restrict__ dir,
+                                                int64_t ray, bool act, int L2, int g, bool vec) {
+    typedef typename Mfma<P>::vec Vec;
+    EncIn<P, F> in;
+    const P* row = enc + (act ? ray : 0) * L2;
+#pragma unroll
+    for (int c = 0; c < F / 32; ++c) {
+        const int k0 = 32 * c + 8 * g;
+        Vec v;
+        if (act && vec && k0 + 8 <= L2) {
+            v = *reinterpret_cast<const Vec*>(row + k0);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i] = act && k0 + i < L2 ? row[k0 + i] : P(0.f);
+        }
+        in.e[c] = v;
+    }
+    in.dx = act ? dir[3 * ray] : 0.f;
+    in.dy = act ? dir[3 * ray + 1] : 0.f;
+    in.dz = act ? dir[3 * ray + 2] : 1.f;
+    return in;
+}
+
+// The network on 16-bit encodings and view directions: enc [n][2L] of the
+// precision's 16-bit type (P), dir [n][3] FP32.  Lane (g, r) loads exactly
+// its B operands of ray r (feature slots 32c + 8g .. +7 of the row, one
+// 16-byte load per chunk when `vec` says rows are 16-byte aligned) and
+// computes the SH values of the unit direction itself, as the shading
+// kernel does, so the input is 4L + 12 bytes per ray instead of
+// 4 (2L + 16).  The next block's inputs are requested before the current
+// block's network runs.
+template <class P, int LPG>
+__global__ __launch_bounds__(kThreads) void k_mlp_enc(ModelC m, const P* __restrict__ enc,
+                                                      const float* __restrict__ dir, int64_t n,
+                                                      float* __restrict__ rgba, bool vec) {
+    typedef Mfma<P> M;
+    typedef typename M::vec Vec;
+    typedef ShadeShape<P, LPG> S;
+    static_assert(S::V == 8, "16-bit operands only");
+    extern __shared__ float4 lds_v[];
+    Vec* W = reinterpret_cast<Vec*>(lds_v);
+    stage_weights<P>(m.weights, m.n_levels, S::F, W);
+    __syncthreads();
+    const int L2 = 2 * m.n_levels;
+    const int lane = __lane_id(), g = lane >> 4, r = lane & 15;
+    // the lane's weight fragments, loaded once: no LDS reads in the loop
+    WReg<Vec, weight_frags<P, S::F>()> wr;
+#pragma unroll
+    for (int f = 0; f < weight_frags<P, S::F>(); ++f) wr.w[f] = W[f * 64 + lane];
+    const int64_t stride = int64_t(gridDim.x) * (kThreads / 64);
+    int64_t blk = int64_t(blockIdx.x) * (kThreads / 64) + threadIdx.x / 64;
+    EncIn<P, S::F> cur = load_enc<P, S::F>(enc, dir, blk * 16 + r, blk * 16 + r < n, L2, g, vec);
+    for (; blk * 16 < n; blk += stride) {
+        const int64_t ray = blk * 16 + r, nray = (blk + stride) * 16 + r;
+        const EncIn<P, S::F> nxt = load_enc<P, S::F>(enc, dir, nray, nray < n, L2, g, vec);
+        Vec b1[S::S1];
+#pragma unroll
+        for (int c = 0; c < S::F / 32; ++c) b1[c] = cur.e[c];
+        const float inv = __builtin_amdgcn_rsqf(cur.dx * cur.dx + cur.dy * cur.dy + cur.dz * cur.dz);
+        float sh[16];
+        sh16(cur.dx * inv, cur.dy * inv, cur.dz * inv, sh);
+        Vec v;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = M::cvt(g == 0 ? sh[i] : (g == 1 ? sh[8 + i] : 0.f));
+        b1[S::S1 - 1] = v;
+        const f32x4 o = mlp_block_w<P, S::F, 0>(wr, b1);
+        // output c = g of ray r: lane (g, r) takes element g of lane r's tile
+        // result, so each lane applies one sigmoid and the 16 rays' 64 outputs
+        // go out as one contiguous store
+        const float t0 = __shfl(o[0], r), t1 = __shfl(o[1], r), t2 = __shfl(o[2], r), t3 = __shfl(o[3], r);
+        const float z = g == 0 ? t0 : (g == 1 ? t1 : (g == 2 ? t2 : t3));
+        if (ray < n) rgba[4 * ray + g] = __builtin_amdgcn_rcpf(1.f + __expf(-z));
+        cur = nxt;
+    }
+}
+
 }  // namespace dev
 }  // namespace inrf
 
@@ -968,6 +1060,18 @@ void launch_mlp_t(const ModelC& c, const float* in, int64_t n, float* rgba, hipS
     // rows start 16-byte aligned when the input array does and d_in = 2L + 16 is a multiple of 4
     const bool vec = (reinterpret_cast<uintptr_t>(in) & 15) == 0 && (c.n_levels % 2) == 0;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, c, in, n, rgba, vec);
+}
+
+template <class P, int LPG>
+void launch_mlp_enc_t(const ModelC& c, const void* enc, const float* dir, int64_t n, float* rgba, hipStream_t s) {
+    const size_t lds = size_t(weight_bytes(ShadeShape<P, LPG>::F, ShadeShape<P, LPG>::V));
+    auto kern = k_mlp_enc<P, LPG>;
+    const int64_t blocks = (n + kThreads / 4 - 1) / (kThreads / 4);  // 16 rays per wave step
+    const unsigned grid = unsigned(std::min<int64_t>(blocks, resident_grid(kern, lds)));
+    // rows start 16-byte aligned when the array does and 2L 16-bit values are a multiple of 16 bytes
+    const bool vec = (reinterpret_cast<uintptr_t>(enc) & 15) == 0 && (c.n_levels % 4) == 0;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, c, reinterpret_cast<const P*>(enc), dir, n, rgba,
+                       vec);
 }
 
 // Levels per lane group (ceil(L / 4)) selects the instantiation.
@@ -1677,6 +1781,31 @@ inrf_status inrf_encode(const inrf_model* m, const float* x, int64_t n, float* e
         if (c.table_dtype == INRF_F32) hipLaunchKernelGGL(dev::k_encode<float>, grid, block, 0, s, c, x, n, enc, slots);
         else hipLaunchKernelGGL(dev::k_encode<__half>, grid, block, 0, s, c, x, n, enc, slots);
         launch_check("k_encode");
+    });
+}
+
+inrf_status inrf_mlp_encoded(const inrf_model* m, int32_t precision, const void* enc, const float* dir, int64_t n,
+                             float* rgba, void* stream) {
+    return guarded("inrf_mlp_encoded", [&] {
+        const dev::ModelC c = make_model(m, false, false);
+        require(m->weights != nullptr, "weights must be set");
+        require(precision == INRF_PREC_FP16 || precision == INRF_PREC_BF16,
+                "inrf_mlp_encoded takes 16-bit encodings: precision must be INRF_PREC_FP16 or INRF_PREC_BF16");
+        require(n >= 0 && n <= (int64_t(1) << 40), "n must be in [0, 2^40]");
+        if (n == 0) return;
+        require(enc && dir && rgba, "NULL buffer");
+        require((reinterpret_cast<uintptr_t>(rgba) & 15) == 0 && (reinterpret_cast<uintptr_t>(enc) & 1) == 0 &&
+                    (reinterpret_cast<uintptr_t>(dir) & 3) == 0,
+                "rgba must be 16-byte, enc 2-byte and dir 4-byte aligned");
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+#define INRF_MLPE(LPG)                                                                   \
+    do {                                                                                \
+        if (precision == INRF_PREC_FP16) launch_mlp_enc_t<_Float16, LPG>(c, enc, dir, n, rgba, s); \
+        else launch_mlp_enc_t<__bf16, LPG>(c, enc, dir, n, rgba, s);                    \
+    } while (0)
+        INRF_LPG_SWITCH(c.n_levels, INRF_MLPE)
+#undef INRF_MLPE
+        launch_check("k_mlp_enc");
     });
 }
 

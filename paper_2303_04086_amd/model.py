@@ -344,6 +344,18 @@ class Renderer:
                                  L.ptr(inputs), n, L.ptr(out), self._stream(stream)))
         return out
 
+    def mlp_encoded(self, enc, dirs, precision="fp16", out=None, stream=None):
+        """The network on 16-bit encodings enc [n, 2L] (float16 for "fp16",
+        bfloat16 for "bf16") and view directions dirs [n, 3] (inrf_mlp_encoded)."""
+        torch = self.torch
+        enc, dirs = enc.contiguous(), dirs.contiguous()
+        n = enc.shape[0]
+        if out is None:
+            out = torch.empty((n, 4), dtype=torch.float32, device=self.device)
+        L.check(L.lib().inrf_mlp_encoded(ctypes.byref(self.desc(next(iter(self.tables)))), PRECISIONS[precision],
+                                         L.ptr(enc), L.ptr(dirs), n, L.ptr(out), self._stream(stream)))
+        return out
+
     # -- gradient ------------------------------------------------------------
     def backward_workspace(self, n_rays: int, table: str = "f32"):
         need = int(L.lib().inrf_backward_workspace_size(ctypes.byref(self.desc(table)), n_rays))

@@ -30,6 +30,13 @@ def psnr(a, b):
 AMB_IDENTICAL_RAYS = 1e-3
 AMB_CAMERA_RAYS = 3e-3
 
+# Grazing hits: an FP32 camera ray fixes its hit point only to about
+# t * 2^-23 / |cos| (cos of the incidence angle), which the finest cell
+# weights (N = 2048) amplify; at |cos| < 0.01 (within 0.6 degrees of
+# grazing, ~1e-4 of a sphere's hit pixels) FP32 colour is reported rather
+# than held to 1e-5.
+GRAZING_COS = 0.01
+
 
 def compare_hits(gpu_tri, ora, max_amb_frac=AMB_IDENTICAL_RAYS):
     """Triangle ids bit-exact on rays the oracle calls unambiguous, and no

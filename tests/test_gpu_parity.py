@@ -113,6 +113,32 @@ def test_mlp_precisions(tiny, R, R16, n, levels):
     assert np.abs(got - oracle.mlp_forward(loud, tiny.weights)).max() <= 1e-5
 
 
+@pytest.mark.parametrize("levels", [4, 5, 16])
+@pytest.mark.parametrize("n", [1, 15, 4099])
+def test_mlp_encoded_inputs(levels, n):
+    """The network on 16-bit encodings and view directions
+    (inrf_mlp_encoded) against the FP64 network on the same 16-bit encoding
+    values and the SH16 of the unit direction: FP16 to 2e-3, BF16 reported
+    (2e-2).  Five levels give rows that are not 16-byte aligned."""
+    w = synth.workload_tiny()
+    w.res = [4 + 3 * k for k in range(levels)]
+    w.weights = synth.xavier_mlp(11 + levels, w.d_in)
+    Rl = make_renderer(w, tables=("f32",))
+    rng = np.random.default_rng(100 * levels + n)
+    enc = rng.normal(0, 0.3, (n, 2 * levels))
+    dirs = rng.normal(size=(n, 3)) * rng.uniform(0.5, 2.0, (n, 1))     # not unit
+    for prec, dt, tol in (("fp16", torch.float16, 2e-3), ("bf16", torch.bfloat16, 2e-2)):
+        e16 = torch.from_numpy(enc).to(dt)
+        want = oracle.mlp_forward(np.concatenate([e16.to(torch.float64).numpy(), oracle.sh_real(dirs)], 1), w.weights)
+        got = Rl.mlp_encoded(e16.cuda(), _dev(dirs.astype(np.float32)), prec).cpu().numpy()
+        err = np.abs(got - want).max()
+        print(f"mlp_encoded L={levels} n={n} {prec}: {err:.2e}")
+        assert err <= tol
+    import paper_2303_04086_amd as P
+    with pytest.raises(P.InrfError):
+        Rl.mlp_encoded(e16.cuda(), _dev(dirs.astype(np.float32)), "fp32")
+
+
 @pytest.mark.parametrize("n_levels", [5, 13])
 def test_mlp_odd_levels_and_unaligned_inputs(n_levels):
     """Rows that are not 16-byte aligned (odd level count, or an input array

@@ -58,6 +58,7 @@ def test_centroid_rays_hit_own_triangle_at_plane_distance(tiny):
     h = oracle.closest_hit(o, -n, V, T)
     assert np.array_equal(h.tri, np.arange(len(T)))
     assert np.allclose(h.t, 0.3, atol=1e-12)
+    assert np.allclose(h.cos, 1.0, atol=1e-12)        # along the normal
     # oblique: t = n.(a - o) / n.d
     rng = np.random.default_rng(0)
     o = cen + 0.02 * n
@@ -68,6 +69,12 @@ def test_centroid_rays_hit_own_triangle_at_plane_distance(tiny):
     t_plane = np.sum(n * (a - o), axis=1) / np.sum(n * d, axis=1)
     assert np.allclose(h.t[ok], t_plane[ok], rtol=1e-12)
     assert ok.mean() > 0.7
+    # incidence cosine: |n.d| of the unit normal and unit direction (a scaled direction gives the same)
+    assert np.allclose(h.cos[ok], np.abs(np.sum(n * d, axis=1))[ok], atol=1e-12)
+    h3 = oracle.closest_hit(o, 3.0 * d, V, T)
+    assert np.allclose(h3.cos[ok], h.cos[ok], atol=1e-12)
+    miss = oracle.closest_hit(o, n, V, T)             # pointing away from its own triangle, out of the sphere
+    assert np.all(np.isnan(miss.cos[miss.tri < 0]))
 
 
 def test_nearest_wins_two_sided_and_ties_lowest_index():
