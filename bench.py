@@ -344,7 +344,8 @@ def train_bench(torch, R, w, steps, batch):
 
 def scene_bench(torch, P, frames, W, H):
     """Multi-object scene: 12 objects with their own tables and networks,
-    merged per pixel by depth; FP16 and FP32 paths at W x H."""
+    merged per pixel by depth; FP16 and FP32 paths at W x H.  Returns the
+    figures and the resident scene (served next)."""
     import synth
     sc = synth.scene_objects(12, W, H)
     t0 = time.time()
@@ -381,9 +382,7 @@ def scene_bench(torch, P, frames, W, H):
                      "ms_per_frame": round(sum(ms) / frames, 4), "p99_ms": round(pct(ms, 99), 4),
                      "hit_fraction_camera0": round(hit, 4)}
         log(f"scene {prec}: {out[prec]}")
-    del S, rs
-    torch.cuda.empty_cache()
-    return out
+    return out, S
 
 
 def single_level_bench(torch, P, frames, W, H, multi_ms):
@@ -495,24 +494,37 @@ def pipelined_bench(torch, P, R, cams, steps, warmup):
     return out
 
 
-def serve_bench(torch, P, R, duration_s, clients=32, rate_hz=30.0):
-    """Serving: `clients` orbiting clients ask for frames at mixed
-    resolutions at Poisson times; requests are admitted in arrival order
-    into batches rendered by one trace and one shading launch, two batches
-    in flight.  Run in real time, then with every request released at once
-    (saturated: aggregate throughput)."""
+SERVE_BUDGET = 2 << 30  # HBM bytes per in-flight batch: workspace + FP32 RGBA images
+
+
+def serve_bench(torch, P, S, center, distance, duration_s, clients=32, rate_hz=30.0):
+    """Serving the resident 12-object scene: `clients` clients on seeded
+    orbits ask for frames at Poisson times, each request's resolution drawn
+    uniformly from 720p/1080p/1440p/4K; requests are admitted in arrival
+    order into batches under an HBM budget per batch (workspace + output),
+    each batch rendered by inrf_render_scene_batch, two batches in flight on
+    their own streams.  Run in real time, then with every request released
+    at once (saturated: aggregate throughput)."""
     import synth
     from paper_2303_04086_amd.serve import Request, Server
-    reqs = [Request(k, t, c) for k, t, c in synth.orbit_requests(clients, duration_s, rate_hz, 13)]
-    out = {"clients": clients, "rate_hz_per_client": rate_hz, "duration_s": duration_s, "requests": len(reqs),
-           "resolutions": "1920x1080, 1280x720, 3840x2160, 800x800 by client", "in_flight": 2}
+    reqs = [Request(k, t, c) for k, t, c in
+            synth.orbit_requests(clients, duration_s, rate_hz, 13, distance=distance, center=center,
+                                 resolutions=synth.SERVING_RESOLUTIONS, per_request=True)]
+    offered = sum(r.pixels for r in reqs) / duration_s / 1e6
+    out = {"target": "12-object scene (inrf_render_scene_batch)", "clients": clients,
+           "rate_hz_per_client": rate_hz, "duration_s": duration_s, "requests": len(reqs),
+           "offered_Mrays_per_s": round(offered, 1),
+           "resolutions": "uniform per request over 1280x720, 1920x1080, 2560x1440, 3840x2160",
+           "hbm_budget_bytes_per_batch": SERVE_BUDGET, "in_flight": 2,
+           "graphs": "not used: the graph leg measures replay against eager launches of the same frame"}
     for prec, table in (("fp16", "f16"), ("fp32", "f32")):
-        S = Server(R, prec, table, pixel_budget=2 * 3840 * 2160)
-        S.run(reqs[: min(len(reqs), 16)], time_scale=0.0)  # warm-up
-        out[prec] = S.run(reqs)
-        out[prec + "_saturated"] = S.run(reqs, time_scale=0.0)
+        srv = Server(S, prec, table, hbm_budget=SERVE_BUDGET, in_flight=2, max_request_pixels=3840 * 2160)
+        srv.run(reqs[: min(len(reqs), 16)], time_scale=0.0)  # warm-up
+        out[prec] = srv.run(reqs)
+        out[prec + "_saturated"] = srv.run(reqs, time_scale=0.0)
         log(f"serve {prec}: {out[prec]}; saturated {out[prec + '_saturated']}")
-        del S
+        del srv
+        torch.cuda.empty_cache()
     return out
 
 
@@ -695,8 +707,13 @@ def main():
                                        "800x800, the 8 cameras 5 times")}
     compulsory = compulsory_bench(torch, P, R, w.cameras[0])
     peaks = peaks_bench(torch) if args.peaks else None
-    scene = scene_bench(torch, P, args.scene_frames, W, H) if args.scene_frames > 0 else None
-    serve = serve_bench(torch, P, R, args.serve_seconds) if args.serve_seconds > 0 else None
+    scene = serve = None
+    if args.scene_frames > 0 or args.serve_seconds > 0:
+        scene, S = scene_bench(torch, P, max(1, args.scene_frames), W, H)
+        if args.serve_seconds > 0:
+            serve = serve_bench(torch, P, S, (2.0, 2.0, 2.0), 6.0, args.serve_seconds)
+        del S
+        torch.cuda.empty_cache()
     nolf = nolf_bench(torch, P, args.nolf_frames, W, H) if args.nolf_frames > 0 else None
     single = (single_level_bench(torch, P, args.single_frames, W, H, out["fp16"][1]["shade_ms_avg"])
               if args.single_frames > 0 else None)

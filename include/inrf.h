@@ -359,6 +359,21 @@ inrf_status inrf_render_scene(const inrf_instance* objects, int32_t n_objects, i
                               const inrf_camera* cam, float* rgba, float* depth, int32_t* tri, int32_t* object,
                               void* ws, int64_t ws_bytes, void* stream);
 
+/* Several cameras over one scene in one pass (the requests of several
+ * clients of a resident scene, Sec. 6, with the per-pixel depth composition
+ * of Sec. 5): one trace launch over all the cameras' tiles, then one
+ * shading launch per object over that object's hit rays from every camera.
+ * cams: host array of n_cameras (1..INRF_MAX_CAMERAS); rgba (and depth,
+ * tri, object if set) hold the images one after another in camera order,
+ * each as inrf_render_scene writes it, and every pixel gets exactly the
+ * value inrf_render_scene gives it.  ws: 256-byte aligned, at least
+ * inrf_scene_batch_workspace_size(n_objects, n_cameras, total pixels)
+ * bytes (-1 on invalid arguments). */
+int64_t inrf_scene_batch_workspace_size(int32_t n_objects, int32_t n_cameras, int64_t n_pixels);
+inrf_status inrf_render_scene_batch(const inrf_instance* objects, int32_t n_objects, int32_t precision,
+                                    const inrf_camera* cams, int32_t n_cameras, float* rgba, float* depth,
+                                    int32_t* tri, int32_t* object, void* ws, int64_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------------------
  * The paper's own i-NOLF form (Sec. 4.2): the hit point comes from a march
  * through cached density texture cubes (Eq. 4, the sample of largest

@@ -25,7 +25,7 @@ EXPORTED = [
     "inrf_forward", "inrf_trace",
     "inrf_encode", "inrf_mlp", "inrf_batch_workspace_size", "inrf_render_batch", "inrf_scene_workspace_size", "inrf_render_scene", "inrf_backward_workspace_size",
     "inrf_backward", "inrf_adam", "inrf_render_nolf", "inrf_shade_nolf", "inrf_camera_rays",
-    "inrf_render_static", "inrf_mlp_encoded",
+    "inrf_render_static", "inrf_mlp_encoded", "inrf_scene_batch_workspace_size", "inrf_render_scene_batch",
 ]
 
 
@@ -133,6 +133,9 @@ def _declare(lib):
         "inrf_render_static": (S, [POINTER(ModelDesc), c_int32, POINTER(CameraDesc), c_void_p, c_void_p, c_void_p,
                                    c_void_p]),
         "inrf_mlp_encoded": (S, [POINTER(ModelDesc), c_int32, c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
+        "inrf_scene_batch_workspace_size": (c_int64, [c_int32, c_int32, c_int64]),
+        "inrf_render_scene_batch": (S, [POINTER(InstanceDesc), c_int32, c_int32, POINTER(CameraDesc), c_int32,
+                                        c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_void_p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

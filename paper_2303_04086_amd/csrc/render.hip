@@ -1378,8 +1378,9 @@ CamC make_camera(const inrf_camera* cam) {
 // K + 1 run starts.
 struct SceneWs {
     int64_t recs, tmp, blk, offsets, runs, seg, end;
-    SceneWs(int64_t n, int k) {
-        const int64_t nb = int64_t(std::max(k, 1)) * (n / 8 + 2), nr = nb / kScanRun + 1;
+    // extra: 2 more tiles per additional camera of a batch
+    SceneWs(int64_t n, int k, int64_t extra = 0) {
+        const int64_t nb = int64_t(std::max(k, 1)) * (n / 8 + 2 + extra), nr = nb / kScanRun + 1;
         recs = kWsHeader;
         tmp = align256(recs + n * int64_t(sizeof(HitRec)));
         blk = align256(tmp + n * int64_t(sizeof(HitRec)));
@@ -1434,17 +1435,18 @@ void make_object(const inrf_instance& in, ObjC& o) {
     }
 }
 
-void run_scene(const inrf_instance* objects, int32_t n_objs, int32_t precision, const inrf_camera* camera,
+template <int NCAM>
+void run_scene(const inrf_instance* objects, int32_t n_objs, int32_t precision, const CamSet<NCAM>& cams,
                float* rgba, float* depth, int32_t* tri, int32_t* obj, void* ws, int64_t ws_bytes, void* stream) {
     check_precision(precision);
     require(n_objs >= 0 && n_objs <= kMaxObjects, "n_objects must be in [0, INRF_MAX_OBJECTS]");
     require(n_objs == 0 || objects != nullptr, "objects is NULL");
-    const CamC cam = make_camera(camera);
-    const int64_t n = int64_t(cam.W) * cam.H;
+    const CamC& last = cams.c[cams.n - 1];
+    const int64_t n = last.pix0 + int64_t(last.W) * last.H;
     require(rgba != nullptr && ws != nullptr, "rgba and workspace must be set");
     require((reinterpret_cast<uintptr_t>(ws) & 255) == 0 && (reinterpret_cast<uintptr_t>(rgba) & 15) == 0,
             "workspace must be 256-byte and rgba 16-byte aligned");
-    const SceneWs L(n, n_objs);
+    const SceneWs L(n, n_objs, 2 * int64_t(cams.n - 1));
     if (ws_bytes < L.end)
         fail(INRF_E_SIZE, "workspace of " + std::to_string(ws_bytes) + " bytes < " + std::to_string(L.end) + " needed");
     SceneC sc;
@@ -1467,9 +1469,9 @@ void run_scene(const inrf_instance* objects, int32_t n_objs, int32_t precision, 
     int32_t* offsets = ws_at<int32_t>(ws, L.offsets);
     int32_t* runs = ws_at<int32_t>(ws, L.runs);
     int32_t* seg = ws_at<int32_t>(ws, L.seg);
-    const int n_tiles = cam.tiles_x * ((cam.H + kTile - 1) / kTile);
+    const int n_tiles = last.tile0 + last.tiles_x * ((last.H + kTile - 1) / kTile);
     const SceneArgs a{rgba, depth, tri, obj, ws_at<HitRec>(ws, L.tmp), blk};
-    hipLaunchKernelGGL(k_trace_scene, dim3(n_tiles), dim3(kThreads), 0, s, sc, cam, a, n_tiles);
+    hipLaunchKernelGGL(k_trace_scene<NCAM>, dim3(n_tiles), dim3(kThreads), 0, s, sc, cams, a, n_tiles);
     launch_check("k_trace_scene");
     if (n_objs == 0) return;
     const int n_blk = n_objs * n_tiles;
@@ -1754,7 +1756,38 @@ inrf_status inrf_render_scene(const inrf_instance* objects, int32_t n_objects, i
                               const inrf_camera* cam, float* rgba, float* depth, int32_t* tri, int32_t* object,
                               void* ws, int64_t ws_bytes, void* stream) {
     return guarded("inrf_render_scene", [&] {
-        run_scene(objects, n_objects, precision, cam, rgba, depth, tri, object, ws, ws_bytes, stream);
+        const dev::CamSet<1> cs{1, 0, {make_camera(cam)}};
+        run_scene<1>(objects, n_objects, precision, cs, rgba, depth, tri, object, ws, ws_bytes, stream);
+    });
+}
+
+int64_t inrf_scene_batch_workspace_size(int32_t n_objects, int32_t n_cameras, int64_t n_pixels) {
+    if (n_objects < 0 || n_objects > INRF_MAX_OBJECTS || n_cameras < 1 || n_cameras > INRF_MAX_CAMERAS ||
+        n_pixels < 0)
+        return -1;
+    return SceneWs(n_pixels, n_objects, 2 * int64_t(n_cameras - 1)).end;
+}
+
+inrf_status inrf_render_scene_batch(const inrf_instance* objects, int32_t n_objects, int32_t precision,
+                                    const inrf_camera* cams, int32_t n_cameras, float* rgba, float* depth,
+                                    int32_t* tri, int32_t* object, void* ws, int64_t ws_bytes, void* stream) {
+    return guarded("inrf_render_scene_batch", [&] {
+        require(n_cameras >= 1 && n_cameras <= INRF_MAX_CAMERAS, "n_cameras must be in [1, INRF_MAX_CAMERAS]");
+        require(cams != nullptr, "cameras is NULL");
+        dev::CamSet<dev::kMaxCameras> cs;
+        std::memset(&cs, 0, sizeof(cs));
+        cs.n = n_cameras;
+        int64_t pix = 0, tiles = 0;
+        for (int j = 0; j < n_cameras; ++j) {
+            cs.c[j] = make_camera(&cams[j]);
+            cs.c[j].tile0 = int32_t(tiles);
+            cs.c[j].pix0 = pix;
+            pix += int64_t(cs.c[j].W) * cs.c[j].H;
+            tiles += int64_t(cs.c[j].tiles_x) * ((cs.c[j].H + dev::kTile - 1) / dev::kTile);
+            require(pix <= (int64_t(1) << 31) - 1, "batch too large (2^31 pixels)");
+        }
+        require(int64_t(std::max(n_objects, 1)) * tiles <= (int64_t(1) << 31) - 1, "too many tiles x objects");
+        run_scene<dev::kMaxCameras>(objects, n_objects, precision, cs, rgba, depth, tri, object, ws, ws_bytes, stream);
     });
 }
 

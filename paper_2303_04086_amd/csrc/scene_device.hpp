@@ -51,17 +51,27 @@ __device__ __forceinline__ float3 xform(const float* m, const float* c, float3 v
     return r;
 }
 
-__global__ __launch_bounds__(kThreads) void k_trace_scene(SceneC sc, CamC cam, SceneArgs a, int n_tiles) {
+// One workgroup per 16x16 tile of the cameras of `cams` (camera j owns
+// tiles [c[j].tile0, c[j+1].tile0) and pixels from c[j].pix0 on), so the
+// rays of several requests are traced by one launch and their records are
+// grouped by object across all of them.
+template <int NCAM>
+__global__ __launch_bounds__(kThreads) void k_trace_scene(SceneC sc, CamSet<NCAM> cams, SceneArgs a, int n_tiles) {
     __shared__ int wst[(kThreads / 64) * kBvhMaxStack];
     __shared__ int s_cnt[kThreads / 64][kMaxObjects];
     const int lane = __lane_id(), wave = int(threadIdx.x) / 64;
     const int b = blockIdx.x;
+    int j = 0;  // the camera of this tile (wave-uniform)
+    for (int k = 1; k < NCAM && k < cams.n; ++k)
+        if (b >= cams.c[k].tile0) j = k;
+    const CamC& cam = cams.c[j];
     int tx, ty;
-    tile_at(b, cam.tiles_x, (cam.H + kTile - 1) / kTile, tx, ty);
+    tile_at(b - cam.tile0, cam.tiles_x, (cam.H + kTile - 1) / kTile, tx, ty);
     const int row = ty * kTile + 8 * (wave >> 1) + (lane >> 3), col = tx * kTile + 8 * (wave & 1) + (lane & 7);
     const bool valid = row < cam.H && col < cam.W;
-    const int64_t ray = int64_t(row) * cam.W + col;
-    const int64_t base = int64_t(ty) * kTile * cam.W + int64_t(tx) * kTile * min(kTile, cam.H - ty * kTile);
+    const int64_t ray = cam.pix0 + int64_t(row) * cam.W + col;
+    const int64_t base =
+        cam.pix0 + int64_t(ty) * kTile * cam.W + int64_t(tx) * kTile * min(kTile, cam.H - ty * kTile);
     const float3 d = camera_dir(cam, row, col);
     const float3 o = make_float3(cam.o[0], cam.o[1], cam.o[2]);
     const RayPre Rw = ray_setup(o, d);

@@ -265,6 +265,13 @@ class Renderer:
             L.check(L.lib().inrf_render_profiled(*args, arr))
         return rgba
 
+    def batch_workspace_bytes(self, n_cameras: int, n_pixels: int) -> int:
+        """Workspace bytes of a batch of n_cameras cameras with n_pixels in all."""
+        need = int(L.lib().inrf_batch_workspace_size(int(n_cameras), int(n_pixels)))
+        if need < 0:
+            raise ValueError("invalid batch")
+        return need
+
     def render_batch(self, cams, precision="fp32", table="f32", rgba=None, depth=None, tri=None, stream=None,
                      ws=None):
         """Render several cameras in one pass (inrf_render_batch).  Returns
@@ -617,6 +624,7 @@ class Scene:
                            for s, R, t in placements]
         self._ws = None
         self.torch = renderers[0].torch if renderers else None
+        self.device = renderers[0].device if renderers else "cuda"
 
     def instances(self, table: str):
         arr = (L.InstanceDesc * max(1, len(self.objects)))()
@@ -632,6 +640,46 @@ class Scene:
         need = int(L.lib().inrf_scene_workspace_size(len(self.objects), n_rays))
         if need < 0:
             raise ValueError("invalid scene size")
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+        return self._ws
+
+    def batch_workspace_bytes(self, n_cameras: int, n_pixels: int) -> int:
+        """Workspace bytes of a batch of n_cameras cameras with n_pixels in all."""
+        need = int(L.lib().inrf_scene_batch_workspace_size(len(self.objects), int(n_cameras), int(n_pixels)))
+        if need < 0:
+            raise ValueError("invalid scene batch")
+        return need
+
+    def render_batch(self, cams, precision="fp32", table="f32", rgba=None, depth=None, tri=None, obj=None,
+                     stream=None, ws=None):
+        """Several cameras over the scene in one pass (inrf_render_scene_batch).
+        Returns the flat [sum(W*H), 4] RGBA buffer and the per-camera
+        [H, W, 4] views into it; `ws` an optional caller workspace."""
+        import torch
+        cams = list(cams)
+        if not 1 <= len(cams) <= L.MAX_CAMERAS:
+            raise ValueError(f"1..{L.MAX_CAMERAS} cameras per batch")
+        sizes = [int(c.width) * int(c.height) for c in cams]
+        n = sum(sizes)
+        if rgba is None:
+            rgba = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+        if ws is None:
+            ws = self.workspace_bytes(self.batch_workspace_bytes(len(cams), n))
+        inst = self.instances(table)
+        arr = (L.CameraDesc * len(cams))(*[_camera_desc(c) for c in cams])
+        s = stream if stream is not None else torch.cuda.current_stream()
+        L.check(L.lib().inrf_render_scene_batch(inst, len(self.objects), PRECISIONS[precision], arr, len(cams),
+                                                L.ptr(rgba), L.ptr(depth), L.ptr(tri), L.ptr(obj), L.ptr(ws),
+                                                ws.numel(), ctypes.c_void_p(s.cuda_stream)))
+        views, off = [], 0
+        for c, k in zip(cams, sizes):
+            views.append(rgba[off:off + k].view(int(c.height), int(c.width), 4))
+            off += k
+        return rgba, views
+
+    def workspace_bytes(self, need: int):
+        import torch
         if self._ws is None or self._ws.numel() < need:
             self._ws = torch.empty(need, dtype=torch.uint8, device="cuda")
         return self._ws

@@ -1,19 +1,23 @@
-"""Serving many clients from one resident i-NOLF object.
+"""Serving many clients from a resident object or scene.
 
 The paper's platform renders frames for many clients from resident models
 and schedules the work per group of rays (Sec. 1, Sec. 5-6).  Here requests
-(a camera and an arrival time) are admitted in arrival order while a batch
-fits a pixel budget (which bounds the workspace the batch needs in HBM) and
-a camera count, and each batch is rendered by inrf_render_batch: one trace
-launch over all its tiles and one shading launch over all its hit rays, so
-rays of different requests share waves.
+(a camera and an arrival time) are admitted in arrival order into batches
+under an HBM budget: a batch grows while its workspace plus its output
+images fit the budget of one in-flight slot (and at most
+INRF_MAX_CAMERAS cameras).  Each batch is rendered in one pass over all its
+rays -- inrf_render_batch for one object, inrf_render_scene_batch for a
+scene (one trace launch over every camera's tiles, then the shading grouped
+by object across the requests) -- so rays of different requests share
+waves.
 
-The loop runs in real time.  Up to `in_flight` batches are on the device at
-once, each on a stream (default priority) with its own workspace and output
-buffer, so that a batch's trace (ALU-bound) overlaps the shading (bound by
-HBM gathers) of the batch before it; a new batch is formed as soon as a
-slot frees up.  A request's latency is the host time at which its batch was
-seen complete minus its arrival time.
+The loop runs in real time (continuous batching).  Up to `in_flight`
+batches are on the device at once, each on a stream (default priority)
+with its own workspace and output buffer, allocated once; a new batch is
+formed from the queue as soon as a slot frees up, so requests that arrive
+while others render are admitted as slots and memory free up, and their
+work overlaps on the device.  A request's latency is the host time at which
+its batch was seen complete minus its arrival time.
 """
 from __future__ import annotations
 
@@ -40,22 +44,29 @@ def _pct(v, q):
 
 
 class Server:
-    def __init__(self, renderer, precision: str = "fp16", table: str = "f16", pixel_budget: int = 2 * 3840 * 2160,
-                 max_batch: int = L.MAX_CAMERAS, in_flight: int = 2, max_request_pixels: int = 3840 * 2160):
+    """target: a Renderer or a Scene (anything with render_batch and
+    batch_workspace_bytes).  hbm_budget: bytes of device memory one batch
+    may hold, its workspace followed by its FP32 RGBA images; the server
+    allocates exactly that much per in-flight slot, once, and every batch it
+    forms fits in it.  max_request_pixels, if given, is checked against the
+    budget up front."""
+
+    def __init__(self, target, precision: str = "fp16", table: str = "f16", hbm_budget: int = 1 << 30,
+                 max_batch: int = L.MAX_CAMERAS, in_flight: int = 2, max_request_pixels: int | None = None):
         import torch
-        self.R, self.precision, self.table = renderer, precision, table
-        self.pixel_budget, self.max_batch = int(pixel_budget), int(min(max_batch, L.MAX_CAMERAS))
+        self.T, self.precision, self.table = target, precision, table
+        self.max_batch = int(min(max_batch, L.MAX_CAMERAS))
+        self.budget = int(hbm_budget)
         self.torch = torch
-        # a batch holds at most pixel_budget pixels, or one request larger than that
-        cap = max(self.pixel_budget, int(max_request_pixels))
-        need = int(L.lib().inrf_batch_workspace_size(self.max_batch, cap))
-        if need < 0:
-            raise ValueError("invalid server limits")
-        self.cap = cap
-        # per slot: stream, output buffer and workspace, allocated once
-        self.slots = [(torch.cuda.Stream(device=renderer.device),
-                       torch.empty((cap, 4), dtype=torch.float32, device=renderer.device),
-                       torch.empty(need, dtype=torch.uint8, device=renderer.device)) for _ in range(int(in_flight))]
+        if max_request_pixels is not None and self.cost(1, int(max_request_pixels)) > self.budget:
+            raise ValueError("the HBM budget cannot hold one request of the largest size")
+        self.slots = [(torch.cuda.Stream(device=target.device),
+                       torch.empty(self.budget, dtype=torch.uint8, device=target.device))
+                      for _ in range(int(in_flight))]
+
+    def cost(self, n_cameras: int, n_pixels: int) -> int:
+        """HBM bytes a batch holds: its workspace and its RGBA images."""
+        return self.T.batch_workspace_bytes(n_cameras, n_pixels) + 16 * int(n_pixels)
 
     def run(self, requests, on_batch=None, time_scale: float = 1.0) -> dict:
         """Serve `requests` (any order); request r is released at
@@ -65,12 +76,12 @@ class Server:
         torch = self.torch
         todo = sorted(requests, key=lambda r: r.arrival_s)
         for r in todo:
-            if r.pixels > self.cap:
-                raise ValueError("a request is larger than the server's output buffer")
+            if self.cost(1, r.pixels) > self.budget:
+                raise ValueError("a request is larger than the HBM budget of one batch")
         free = list(range(len(self.slots)))
-        queue, flight, lat, sizes = [], [], [], []
+        queue, flight, lat, sizes, held = [], [], [], [], []
         pixels, busy, busy_from, i = 0, 0.0, None, 0
-        torch.cuda.current_stream(self.R.device).synchronize()
+        torch.cuda.current_stream(self.T.device).synchronize()
         t0 = time.perf_counter()
         while i < len(todo) or queue or flight:
             now = time.perf_counter() - t0
@@ -88,26 +99,33 @@ class Server:
                 if not flight:
                     busy += done - busy_from
             if queue and free:
-                batch, pix = [], 0
-                while queue and len(batch) < self.max_batch and (not batch or pix + queue[0].pixels <= self.pixel_budget):
+                batch = [queue.pop(0)]
+                pix = batch[0].pixels
+                while (queue and len(batch) < self.max_batch
+                       and self.cost(len(batch) + 1, pix + queue[0].pixels) <= self.budget):
                     pix += queue[0].pixels
                     batch.append(queue.pop(0))
                 slot = free.pop(0)
-                stream, rgba, ws = self.slots[slot]
+                stream, buf = self.slots[slot]
+                # the slot's bytes: workspace (a multiple of 256 bytes), then the images
+                need = self.T.batch_workspace_bytes(len(batch), pix)
+                rgba = buf[need:need + 16 * pix].view(torch.float32).view(pix, 4)
                 if not flight:
                     busy_from = time.perf_counter() - t0
-                _, views = self.R.render_batch([r.camera for r in batch], self.precision, self.table,
-                                               rgba=rgba[:pix], stream=stream, ws=ws)
+                _, views = self.T.render_batch([r.camera for r in batch], self.precision, self.table,
+                                               rgba=rgba, stream=stream, ws=buf[:need])
                 ev = torch.cuda.Event()
                 ev.record(stream)
                 flight.append((slot, batch, ev, views))
                 pixels += pix
                 sizes.append(len(batch))
+                held.append(self.cost(len(batch), pix))
             elif not flight and i < len(todo):
                 time.sleep(max(0.0, min(1e-3, todo[i].arrival_s * time_scale - now)))
         span = time.perf_counter() - t0
         return {"requests": len(lat), "batches": len(sizes), "mean_batch": round(sum(sizes) / max(1, len(sizes)), 2),
-                "in_flight": len(self.slots),
+                "in_flight": len(self.slots), "hbm_budget_bytes": self.budget,
+                "max_batch_bytes": max(held) if held else 0,
                 "p50_latency_ms": round(_pct(lat, 50) * 1e3, 3), "p99_latency_ms": round(_pct(lat, 99) * 1e3, 3),
                 "Mrays_per_s": round(pixels / max(busy, 1e-12) / 1e6, 1), "busy_s": round(busy, 4),
                 "span_s": round(span, 4)}

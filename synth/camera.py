@@ -71,14 +71,19 @@ def random_cameras(n: int, seed: int, distance: float = 2.0, width: int = 3840, 
     return [look_at_camera(c + distance * x, c, fov_y_deg, width, height) for x in d]
 
 
+SERVING_RESOLUTIONS = ((1280, 720), (1920, 1080), (2560, 1440), (3840, 2160))
+
+
 def orbit_requests(n_clients: int, duration_s: float, rate_hz: float, seed: int, distance: float = 2.0,
                    resolutions=((1920, 1080), (1280, 720), (3840, 2160), (800, 800)), center=(0.5, 0.5, 0.5),
-                   fov_y_deg: float = 40.0):
+                   fov_y_deg: float = 40.0, per_request: bool = False):
     """Client requests for a serving test: client k orbits `center` at
     `distance` about its own seeded axis at its own angular speed (0.5..2
-    rad/s) and asks for frames at resolution resolutions[k % len] at Poisson
-    times of rate `rate_hz` within [0, duration_s).  Returns a list of
-    (client, arrival time, Camera), sorted by time."""
+    rad/s) and asks for frames at Poisson times of rate `rate_hz` within
+    [0, duration_s).  The resolution is resolutions[k % len] for all of
+    client k's frames, or, with per_request, drawn uniformly from
+    `resolutions` for every request.  Returns a list of (client, arrival
+    time, Camera), sorted by time."""
     rng = np.random.Generator(np.random.PCG64(seed))
     c = np.asarray(center, np.float64)
     out = []
@@ -93,6 +98,8 @@ def orbit_requests(n_clients: int, duration_s: float, rate_hz: float, seed: int,
         while t < duration_s:
             a = omega * t
             d = start * math.cos(a) + np.cross(axis, start) * math.sin(a)   # rotation of start about axis
+            if per_request:
+                W, H = resolutions[int(rng.integers(len(resolutions)))]
             out.append((k, float(t), look_at_camera(c + distance * d, c, fov_y_deg, W, H)))
             t += rng.exponential(1.0 / rate_hz)
     out.sort(key=lambda r: r[1])
