@@ -196,6 +196,41 @@ __device__ __forceinline__ void load_inputs(const void* tile_row, float dx, floa
     }
 }
 
+// The first layer's B operands of this lane from row r of the block's tile
+// holding the ray's F feature slots followed by its 16 SH values (both in the
+// tile's element type: the precision's 16-bit type, or FP32), and, with X = 1,
+// the extra input `extra` of that ray.  The SH values are computed once per
+// ray by the lane that owns the ray, rather than by every lane group.
+template <class P, int F, int X = 0>
+__device__ __forceinline__ void load_inputs_row(const void* tile_row, typename Mfma<P>::vec* b, float extra = 0.f) {
+    typedef Mfma<P> M;
+    constexpr int V = M::V, S1 = l1_steps(F, V, X);
+    const int g = __lane_id() >> 4;
+    if constexpr (V == 1) {
+        const float* row = reinterpret_cast<const float*>(tile_row);
+#pragma unroll
+        for (int j = 0; j < F / 16 + 1; ++j) {  // the last read is SH values 4g .. 4g + 3
+            const f32x4 v = *reinterpret_cast<const f32x4*>(row + 16 * j + 4 * g);
+            b[4 * j + 0] = v[0];
+            b[4 * j + 1] = v[1];
+            b[4 * j + 2] = v[2];
+            b[4 * j + 3] = v[3];
+        }
+        if constexpr (X == 1) b[F / 4 + 4] = g == 0 ? extra : 0.f;
+    } else {
+        typedef typename M::vec Vec;
+        const Vec* row = reinterpret_cast<const Vec*>(tile_row);
+#pragma unroll
+        for (int c = 0; c < F / 32; ++c) b[c] = row[4 * c + g];
+        Vec v = row[F / 8 + (g & 1)];  // SH values 8g .. 8g + 7 for g < 2
+        if (g >= 2) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i] = M::cvt(X == 1 && g == 2 && i == 0 ? extra : 0.f);
+        }
+        b[S1 - 1] = v;
+    }
+}
+
 // This lane's A operand of weight fragment f, from the LDS image (WLds) or
 // from registers the lane loaded it into once (WReg).
 template <class Vec>
@@ -210,73 +245,105 @@ struct WReg {
     __device__ Vec operator()(int f) const { return w[f]; }
 };
 
-// The network for this lane's block of 16 rays given its first-layer B
-// operands.  Returns D of the output tile: for lanes l < 16, element i is
-// pre-sigmoid output i of ray l.
-template <class P, int F, int X = 0>
-__device__ __forceinline__ f32x4 mlp_block(const typename Mfma<P>::vec* __restrict__ W,
-                                           const typename Mfma<P>::vec* b1);
+// ReLU of hidden values and their conversion to the next layer's B operand.
+// For 16-bit operands the values are converted first and the ReLU is a
+// packed integer max with 0 on the 16-bit patterns: a negative value (sign
+// bit set, -0 included) becomes +0, any other is kept, which is exactly the
+// conversion of max(x, 0) in half the instructions and without the operand
+// canonicalisation a float max needs.  FP32 does the same on 32-bit patterns.
+typedef short i16x8 __attribute__((ext_vector_type(8)));
 
-template <class P, int F, int X, class WA>
-__device__ __forceinline__ f32x4 mlp_block_w(const WA& wa, const typename Mfma<P>::vec* b1) {
+__device__ __forceinline__ float relu_bits(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
+template <class P>
+__device__ __forceinline__ typename Mfma<P>::vec relu_pack(const f32x4& lo, const f32x4& hi) {
+    typedef Mfma<P> M;
+    typedef float f32x8 __attribute__((ext_vector_type(8)));
+    const f32x8 x = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    const typename M::vec v = __builtin_convertvector(x, typename M::vec);
+    const i16x8 z = {0, 0, 0, 0, 0, 0, 0, 0};
+    return __builtin_bit_cast(typename M::vec, __builtin_elementwise_max(__builtin_bit_cast(i16x8, v), z));
+}
+
+// The network for NB blocks of 16 rays each, given each block's first-layer
+// B operands b1[blk][step]; the blocks' instructions are interleaved step by
+// step, so one block's matrix instructions run while another's results are
+// converted.  o[blk] is D of the output tile: for lanes l < 16, element i is
+// pre-sigmoid output i of ray l of that block.
+template <class P, int F, int X, int NB, class WA>
+__device__ __forceinline__ void mlp_blocks_w(const WA& wa, const typename Mfma<P>::vec (*b1)[l1_steps(F, Mfma<P>::V, X)],
+                                             f32x4* o) {
     typedef Mfma<P> M;
     typedef typename M::vec Vec;
     constexpr int V = M::V, S1 = l1_steps(F, V, X), SH = hid_steps(V);
-    f32x4 h1[4];
+    f32x4 h1[NB][4];
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) h1[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < NB; ++k)
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) h1[k][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < S1; ++s) {
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) h1[mt] = M::op(wa(mt * S1 + s), b1[s], h1[mt]);
+        for (int mt = 0; mt < 4; ++mt) {
+            const Vec w = wa(mt * S1 + s);
+#pragma unroll
+            for (int k = 0; k < NB; ++k) h1[k][mt] = M::op(w, b1[k][s], h1[k][mt]);
+        }
         __builtin_amdgcn_sched_barrier(0);  // keep weight loads next to their use
     }
     constexpr int F2 = 4 * S1, F3 = F2 + 4 * SH;  // first fragments of W2 and W3
-    Vec b2[SH];
+    Vec b2[NB][SH];
 #pragma unroll
-    for (int s = 0; s < SH; ++s) {
-        if constexpr (V == 1) {
-            b2[s] = fmaxf(h1[s / 4][s % 4], 0.f);
-        } else {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                b2[s][i] = M::cvt(fmaxf(h1[2 * s][i], 0.f));
-                b2[s][4 + i] = M::cvt(fmaxf(h1[2 * s + 1][i], 0.f));
-            }
-        }
-    }
-    f32x4 h2[4];
-#pragma unroll
-    for (int ot = 0; ot < 4; ++ot) {
-        h2[ot] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < NB; ++k)
 #pragma unroll
         for (int s = 0; s < SH; ++s) {
-            h2[ot] = M::op(wa(F2 + ot * SH + s), b2[s], h2[ot]);
+            if constexpr (V == 1) b2[k][s] = relu_bits(h1[k][s / 4][s % 4]);
+            else b2[k][s] = relu_pack<P>(h1[k][2 * s], h1[k][2 * s + 1]);
+        }
+    f32x4 h2[NB][4];
+#pragma unroll
+    for (int ot = 0; ot < 4; ++ot) {
+#pragma unroll
+        for (int k = 0; k < NB; ++k) h2[k][ot] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < SH; ++s) {
+            const Vec w = wa(F2 + ot * SH + s);
+#pragma unroll
+            for (int k = 0; k < NB; ++k) h2[k][ot] = M::op(w, b2[k][s], h2[k][ot]);
             if ((s & 3) == 3) __builtin_amdgcn_sched_barrier(0);
         }
         __builtin_amdgcn_sched_barrier(0);
     }
-    Vec b3[SH];
+    Vec b3[NB][SH];
 #pragma unroll
-    for (int s = 0; s < SH; ++s) {
-        if constexpr (V == 1) {
-            b3[s] = fmaxf(h2[s / 4][s % 4], 0.f);
-        } else {
+    for (int k = 0; k < NB; ++k)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                b3[s][i] = M::cvt(fmaxf(h2[2 * s][i], 0.f));
-                b3[s][4 + i] = M::cvt(fmaxf(h2[2 * s + 1][i], 0.f));
-            }
+        for (int s = 0; s < SH; ++s) {
+            if constexpr (V == 1) b3[k][s] = relu_bits(h2[k][s / 4][s % 4]);
+            else b3[k][s] = relu_pack<P>(h2[k][2 * s], h2[k][2 * s + 1]);
         }
-    }
-    f32x4 o = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < NB; ++k) o[k] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < SH; ++s) {
-        o = M::op(wa(F3 + s), b3[s], o);
+        const Vec w = wa(F3 + s);
+#pragma unroll
+        for (int k = 0; k < NB; ++k) o[k] = M::op(w, b3[k][s], o[k]);
         if ((s & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
+}
+
+// One block of 16 rays (NB = 1).
+template <class P, int F, int X, class WA>
+__device__ __forceinline__ f32x4 mlp_block_w(const WA& wa, const typename Mfma<P>::vec* b1) {
+    f32x4 o;
+    mlp_blocks_w<P, F, X, 1>(wa, reinterpret_cast<const typename Mfma<P>::vec(*)[l1_steps(F, Mfma<P>::V, X)]>(b1), &o);
     return o;
 }
+
+template <class P, int F, int X = 0>
+__device__ __forceinline__ f32x4 mlp_block(const typename Mfma<P>::vec* __restrict__ W,
+                                           const typename Mfma<P>::vec* b1);
 
 template <class P, int F, int X>
 __device__ __forceinline__ f32x4 mlp_block(const typename Mfma<P>::vec* __restrict__ W,

@@ -550,6 +550,15 @@ __global__ __launch_bounds__(kThreads) void k_compact(const int2* __restrict__ b
 
 // ------------------------------------------------------------- shading ----
 
+// Network kernels are declared to fit in at most 256 registers per lane (at
+// least two waves per SIMD), which they do anyway; with that bound the
+// compiler keeps matrix-instruction results in ordinary vector registers
+// instead of accumulation registers that must be copied out before the
+// ReLU and the next layer.
+#ifndef INRF_MFMA_VGPR
+#define INRF_MFMA_VGPR __attribute__((amdgpu_waves_per_eu(2)))
+#endif
+
 template <class P>
 struct TileElem {
     typedef P type;  // FP16/BF16 tiles hold the MMA operand type
@@ -586,7 +595,8 @@ struct ShadeShape {
     static constexpr int V = Mfma<P>::V;
     static constexpr int LMAX = 4 * LPG;  // levels the instantiation handles
     static constexpr int F = feature_slots(LMAX, V);
-    static constexpr int STRIDE = F + (V == 1 ? 4 : 8);  // elements per row, keeps 16-byte alignment
+    // a row: F feature slots, 16 SH values, padding that keeps rows 16-byte aligned
+    static constexpr int STRIDE = F + INRF_SH_DIM + (V == 1 ? 4 : 8);
     static constexpr int S1 = l1_steps(F, V, X);
     static constexpr size_t tile_bytes = 16 * STRIDE * sizeof(typename TileElem<P>::type);
     static constexpr size_t lds_bytes = size_t(weight_bytes(F, V, X)) + (kThreads / 64) * tile_bytes;
@@ -603,7 +613,7 @@ struct ShadeShape {
 // diffuse colour and tint of the hit, which the outputs complete as
 // (c_d + t c_s, alpha).
 template <class TableT, class P, int LPG, bool NOLF = false>
-__global__ __launch_bounds__(kThreads) void k_shade(ModelC m, const HitRec* __restrict__ recs,
+__global__ __launch_bounds__(kThreads) INRF_MFMA_VGPR void k_shade(ModelC m, const HitRec* __restrict__ recs,
                                                     const int32_t* __restrict__ first,
                                                     const int32_t* __restrict__ counter, float* __restrict__ rgba) {
     constexpr int X = NOLF ? 1 : 0;
@@ -630,12 +640,16 @@ __global__ __launch_bounds__(kThreads) void k_shade(ModelC m, const HitRec* __re
 #pragma unroll
         for (int k = 2 * S::LMAX; k < S::F; ++k) e[k] = 0.f;
         gather_levels<TableT, 0, S::LMAX>(m, h.x, h.y, h.z, e);
+        float sh[INRF_SH_DIM];  // of the lane's own ray (unit direction)
+        sh16(h.dx, h.dy, h.dz, sh);
         const int nb = int(min<int64_t>(4, (int64_t(n) - base + 15) / 16));
         for (int b = 0; b < nb; ++b) {
             if (g == b) {
                 T* row = tile + r * S::STRIDE;
 #pragma unroll
                 for (int k = 0; k < S::F; ++k) row[k] = T(e[k]);
+#pragma unroll
+                for (int k = 0; k < INRF_SH_DIM; ++k) row[S::F + k] = T(sh[k]);
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -643,8 +657,7 @@ __global__ __launch_bounds__(kThreads) void k_shade(ModelC m, const HitRec* __re
             const int src = 16 * b + r;
             Vec b1[S::S1];
             const float extra = NOLF ? __shfl(__int_as_float(h.pad), src) : 0.f;
-            load_inputs<P, S::F, X>(tile + r * S::STRIDE, __shfl(h.dx, src), __shfl(h.dy, src), __shfl(h.dz, src),
-                                    b1, extra);
+            load_inputs_row<P, S::F, X>(tile + r * S::STRIDE, b1, extra);
             const int out = __shfl(h.out, src);
             const f32x4 o = mlp_block<P, S::F, X>(W, b1);
             if (g == 0 && base + src < n) {
@@ -714,7 +727,7 @@ __device__ __forceinline__ f32x4 load_inputs4(const float* a, int k, int limit, 
 // The network alone on caller inputs [n][d_in] in natural order: lane
 // (g, r) loads exactly its B operands of ray r straight from memory.
 template <class P, int LPG>
-__global__ __launch_bounds__(kThreads) void k_mlp(ModelC m, const float* __restrict__ x, int64_t n,
+__global__ __launch_bounds__(kThreads) INRF_MFMA_VGPR void k_mlp(ModelC m, const float* __restrict__ x, int64_t n,
                                                   float* __restrict__ rgba, bool vec) {
     typedef Mfma<P> M;
     typedef typename M::vec Vec;
@@ -780,86 +793,122 @@ __global__ __launch_bounds__(kThreads) void k_mlp(ModelC m, const float* __restr
 // 4 (2L + 16).
 // Inputs of ray `ray` for lane group g: the chunks of its 16-bit encoding
 // row this lane supplies, and the view direction.
-template <class P, int F>
-struct EncIn {
-    typename Mfma<P>::vec e[F / 32];
-    float dx, dy, dz;
-};
-
-template <class P, int F>
-__device__ __forceinline__ EncIn<P, F> load_enc(const P* __restrict__ enc, const float* __restrict__ dir,
-                                                int64_t ray, bool act, int L2, int g, bool vec) {
+// Feature slots 32c + 8g .. +7 of the row (c < F / 32) of an encoding of 2L
+// 16-bit values, zeros past the row and for inactive rays.  VEC: rows are
+// 16-byte aligned and 2L is a multiple of 8, so a chunk lies wholly inside
+// the row or wholly past it and is one 16-byte load; otherwise value by
+// value.
+template <class P, int F, bool VEC>
+__device__ __forceinline__ void load_enc(const P* __restrict__ enc, int64_t ray, bool act, int L2, int g,
+                                         typename Mfma<P>::vec* e) {
     typedef typename Mfma<P>::vec Vec;
-    EncIn<P, F> in;
     const P* row = enc + (act ? ray : 0) * L2;
 #pragma unroll
     for (int c = 0; c < F / 32; ++c) {
         const int k0 = 32 * c + 8 * g;
-        Vec v;
-        if (act && vec && k0 + 8 <= L2) {
-            v = *reinterpret_cast<const Vec*>(row + k0);
+        Vec v = {};
+        if constexpr (VEC) {
+            if (act && k0 < L2) v = *reinterpret_cast<const Vec*>(row + k0);
         } else {
 #pragma unroll
-            for (int i = 0; i < 8; ++i) v[i] = act && k0 + i < L2 ? row[k0 + i] : P(0.f);
+            for (int i = 0; i < 8; ++i)
+                if (act && k0 + i < L2) v[i] = row[k0 + i];
         }
-        in.e[c] = v;
+        e[c] = v;
     }
-    in.dx = act ? dir[3 * ray] : 0.f;
-    in.dy = act ? dir[3 * ray + 1] : 0.f;
-    in.dz = act ? dir[3 * ray + 2] : 1.f;
-    return in;
 }
 
+// Row stride (elements) of the per-wave SH tile of k_mlp_enc: 16 values and
+// padding, rows 16-byte aligned.
+constexpr int kShRow = INRF_SH_DIM + 8;
+
+#ifndef KMLP_BLOCKS
+#define KMLP_BLOCKS 4
+#endif
+constexpr int kMlpBlocks = KMLP_BLOCKS;  // blocks of 16 rays per wave step of k_mlp_enc (1, 2 or 4)
+
 // The network on 16-bit encodings and view directions: enc [n][2L] of the
-// precision's 16-bit type (P), dir [n][3] FP32.  Lane (g, r) loads exactly
-// its B operands of ray r (feature slots 32c + 8g .. +7 of the row, one
-// 16-byte load per chunk when `vec` says rows are 16-byte aligned) and
-// computes the SH values of the unit direction itself, as the shading
-// kernel does, so the input is 4L + 12 bytes per ray instead of
-// 4 (2L + 16).  The next block's inputs are requested before the current
-// block's network runs.
-template <class P, int LPG>
-__global__ __launch_bounds__(kThreads) void k_mlp_enc(ModelC m, const P* __restrict__ enc,
-                                                      const float* __restrict__ dir, int64_t n,
-                                                      float* __restrict__ rgba, bool vec) {
+// precision's 16-bit type (P), dir [n][3] FP32.  A wave step takes
+// 16 * kMlpBlocks rays.  The lane that owns a ray (lane l of block l / 16)
+// normalises its direction, computes its 16 SH values once and writes them
+// to a row of the wave's LDS tile; for each block, lane (g, r) then loads
+// its B operands of ray r directly (feature slots 32c + 8g .. +7 of the
+// encoding row) and reads SH values 8g .. 8g + 7 of the ray from the tile.
+// The input is 4L + 12 bytes per ray instead of 4 (2L + 16).
+template <class P, int LPG, bool VEC>
+__global__ __launch_bounds__(kThreads) INRF_MFMA_VGPR void k_mlp_enc(ModelC m, const P* __restrict__ enc,
+                                                                     const float* __restrict__ dir, int64_t n,
+                                                                     float* __restrict__ rgba) {
     typedef Mfma<P> M;
     typedef typename M::vec Vec;
     typedef ShadeShape<P, LPG> S;
     static_assert(S::V == 8, "16-bit operands only");
+    constexpr int NB = kMlpBlocks, RAYS = 16 * NB;
     extern __shared__ float4 lds_v[];
     Vec* W = reinterpret_cast<Vec*>(lds_v);
     stage_weights<P>(m.weights, m.n_levels, S::F, W);
+    P* shtile = reinterpret_cast<P*>(reinterpret_cast<char*>(lds_v) + weight_bytes(S::F, S::V)) +
+                (threadIdx.x / 64) * RAYS * kShRow;
     __syncthreads();
     const int L2 = 2 * m.n_levels;
     const int lane = __lane_id(), g = lane >> 4, r = lane & 15;
-    // the lane's weight fragments, loaded once: no LDS reads in the loop
+    // the lane's weight fragments, loaded once: no weight reads from LDS in the loop
     WReg<Vec, weight_frags<P, S::F>()> wr;
 #pragma unroll
     for (int f = 0; f < weight_frags<P, S::F>(); ++f) wr.w[f] = W[f * 64 + lane];
     const int64_t stride = int64_t(gridDim.x) * (kThreads / 64);
-    int64_t blk = int64_t(blockIdx.x) * (kThreads / 64) + threadIdx.x / 64;
-    EncIn<P, S::F> cur = load_enc<P, S::F>(enc, dir, blk * 16 + r, blk * 16 + r < n, L2, g, vec);
-    for (; blk * 16 < n; blk += stride) {
-        const int64_t ray = blk * 16 + r, nray = (blk + stride) * 16 + r;
-        const EncIn<P, S::F> nxt = load_enc<P, S::F>(enc, dir, nray, nray < n, L2, g, vec);
-        Vec b1[S::S1];
+    for (int64_t step = int64_t(blockIdx.x) * (kThreads / 64) + threadIdx.x / 64; step * RAYS < n; step += stride) {
+        const int64_t base = step * RAYS;
+        Vec e[NB][S::F / 32];
 #pragma unroll
-        for (int c = 0; c < S::F / 32; ++c) b1[c] = cur.e[c];
-        const float inv = __builtin_amdgcn_rsqf(cur.dx * cur.dx + cur.dy * cur.dy + cur.dz * cur.dz);
-        float sh[16];
-        sh16(cur.dx * inv, cur.dy * inv, cur.dz * inv, sh);
-        Vec v;
+        for (int k = 0; k < NB; ++k) {
+            const int64_t ray = base + 16 * k + r;
+            load_enc<P, S::F, VEC>(enc, ray, ray < n, L2, g, e[k]);
+        }
+        if (lane < RAYS) {  // the lane's own ray: its SH row
+            const int64_t ray = base + lane;
+            const bool act = ray < n;
+            const float dx = act ? dir[3 * ray] : 0.f, dy = act ? dir[3 * ray + 1] : 0.f,
+                        dz = act ? dir[3 * ray + 2] : 1.f;
+            const float inv = __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
+            float sh[16];
+            sh16(dx * inv, dy * inv, dz * inv, sh);
+            Vec lo, hi;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) v[i] = M::cvt(g == 0 ? sh[i] : (g == 1 ? sh[8 + i] : 0.f));
-        b1[S::S1 - 1] = v;
-        const f32x4 o = mlp_block_w<P, S::F, 0>(wr, b1);
-        // output c = g of ray r: lane (g, r) takes element g of lane r's tile
-        // result, so each lane applies one sigmoid and the 16 rays' 64 outputs
-        // go out as one contiguous store
-        const float t0 = __shfl(o[0], r), t1 = __shfl(o[1], r), t2 = __shfl(o[2], r), t3 = __shfl(o[3], r);
-        const float z = g == 0 ? t0 : (g == 1 ? t1 : (g == 2 ? t2 : t3));
-        if (ray < n) rgba[4 * ray + g] = __builtin_amdgcn_rcpf(1.f + __expf(-z));
-        cur = nxt;
+            for (int i = 0; i < 8; ++i) {
+                lo[i] = M::cvt(sh[i]);
+                hi[i] = M::cvt(sh[8 + i]);
+            }
+            Vec* row = reinterpret_cast<Vec*>(shtile + lane * kShRow);
+            row[0] = lo;
+            row[1] = hi;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            Vec b1[S::S1];
+#pragma unroll
+            for (int c = 0; c < S::F / 32; ++c) b1[c] = e[k][c];
+            Vec v = reinterpret_cast<const Vec*>(shtile + (16 * k + r) * kShRow)[g & 1];
+            if (g >= 2) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) v[i] = M::cvt(0.f);
+            }
+            b1[S::S1 - 1] = v;
+            const f32x4 o = mlp_block_w<P, S::F, 0>(wr, b1);
+            // output c = g of ray r: lane (g, r) takes element g of lane r's
+            // tile result, so each lane applies one sigmoid and the block's
+            // 64 outputs go out as one contiguous store
+            const int64_t ray = base + 16 * k + r;
+            const float t0 = __shfl(o[0], r), t1 = __shfl(o[1], r), t2 = __shfl(o[2], r), t3 = __shfl(o[3], r);
+            const float z = g == 0 ? t0 : (g == 1 ? t1 : (g == 2 ? t2 : t3));
+            if (ray < n) rgba[4 * ray + g] = __builtin_amdgcn_rcpf(1.f + __expf(-z));
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();  // the SH tile is rewritten by the next step
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -1064,14 +1113,15 @@ void launch_mlp_t(const ModelC& c, const float* in, int64_t n, float* rgba, hipS
 
 template <class P, int LPG>
 void launch_mlp_enc_t(const ModelC& c, const void* enc, const float* dir, int64_t n, float* rgba, hipStream_t s) {
-    const size_t lds = size_t(weight_bytes(ShadeShape<P, LPG>::F, ShadeShape<P, LPG>::V));
-    auto kern = k_mlp_enc<P, LPG>;
-    const int64_t blocks = (n + kThreads / 4 - 1) / (kThreads / 4);  // 16 rays per wave step
-    const unsigned grid = unsigned(std::min<int64_t>(blocks, resident_grid(kern, lds)));
+    const size_t lds = size_t(weight_bytes(ShadeShape<P, LPG>::F, ShadeShape<P, LPG>::V)) +
+                       (kThreads / 64) * 16 * kMlpBlocks * kShRow * sizeof(P);
     // rows start 16-byte aligned when the array does and 2L 16-bit values are a multiple of 16 bytes
     const bool vec = (reinterpret_cast<uintptr_t>(enc) & 15) == 0 && (c.n_levels % 4) == 0;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, c, reinterpret_cast<const P*>(enc), dir, n, rgba,
-                       vec);
+    auto kern = vec ? k_mlp_enc<P, LPG, true> : k_mlp_enc<P, LPG, false>;
+    const int64_t per_wg = (kThreads / 64) * 16 * kMlpBlocks;  // rays per workgroup step
+    const int64_t blocks = (n + per_wg - 1) / per_wg;
+    const unsigned grid = unsigned(std::min<int64_t>(blocks, resident_grid(kern, lds)));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, c, reinterpret_cast<const P*>(enc), dir, n, rgba);
 }
 
 // Levels per lane group (ceil(L / 4)) selects the instantiation.
