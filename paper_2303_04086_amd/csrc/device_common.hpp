@@ -99,8 +99,10 @@ struct LevelQuery {
 };
 
 // Cell, hash bases and the eight offset loads of one level.
-__device__ __forceinline__ void level_issue(const ModelC& m, const LevelC& L, float x, float y, float z,
-                                            LevelQuery& q) {
+// The model M is any descriptor with the offset and feature tables `phi`
+// and `table` (the full ModelC, or the shading view of one scene object).
+template <class M>
+__device__ __forceinline__ void level_issue(const M& m, const LevelC& L, float x, float y, float z, LevelQuery& q) {
     int px, py, pz;
     cell_of(x, L.res, px, q.wx);
     cell_of(y, L.res, py, q.wy);
@@ -140,8 +142,8 @@ __device__ __forceinline__ uint32_t level_store(const LevelC& L, const LevelQuer
 }
 
 // Feature loads of the eight corners.
-template <class T>
-__device__ __forceinline__ void level_fetch(const ModelC& m, const LevelC& L, const LevelQuery& q, float2* f,
+template <class T, class M>
+__device__ __forceinline__ void level_fetch(const M& m, const LevelC& L, const LevelQuery& q, float2* f,
                                             int32_t* __restrict__ slots_out) {
     const char* base = reinterpret_cast<const char*>(
         reinterpret_cast<const typename TableRead<T>::elem*>(m.table) + L.slot_off);
@@ -168,8 +170,8 @@ __device__ __forceinline__ float2 level_blend(const LevelQuery& q, const float2*
 
 // One level, optionally writing the eight level-local linear slots
 // (s_z * mbar + s_y) * mbar + s_x to slots_out[0..7] (global memory).
-template <class T>
-__device__ __forceinline__ float2 encode_level(const ModelC& m, const LevelC& L, float x, float y, float z,
+template <class T, class M>
+__device__ __forceinline__ float2 encode_level(const M& m, const LevelC& L, float x, float y, float z,
                                                int32_t* __restrict__ slots_out) {
     LevelQuery q;
     level_issue(m, L, x, y, z, q);
@@ -180,9 +182,9 @@ __device__ __forceinline__ float2 encode_level(const ModelC& m, const LevelC& L,
 
 // Two levels with their offset loads in flight together (x in [0,1]^3; a
 // lane with nothing to do passes a valid dummy point and drops the result).
-template <class T>
-__device__ __forceinline__ void encode_level_pair(const ModelC& m, const LevelC& La, const LevelC& Lb, float x,
-                                                  float y, float z, float2& ea, float2& eb) {
+template <class T, class M>
+__device__ __forceinline__ void encode_level_pair(const M& m, const LevelC& La, const LevelC& Lb, float x, float y,
+                                                  float z, float2& ea, float2& eb) {
     LevelQuery qa, qb;
     level_issue(m, La, x, y, z, qa);
     level_issue(m, Lb, x, y, z, qb);

@@ -534,17 +534,24 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_runs(int32_t* __restrict_
 }
 
 // Packs the workgroups' records into one list in workgroup order (tile
-// raster order for a camera), so the list does not depend on timing.
+// order for a camera), so the list does not depend on timing.  Workgroup b
+// moves the record runs b, b + stride, ... (n_groups of them): one run per
+// workgroup for a single object, every object's run of tile b for a scene
+// (runs stored [object][tile]), so a scene launches one workgroup per tile
+// rather than one per (object, tile).
 __global__ __launch_bounds__(kThreads) void k_compact(const int2* __restrict__ blk, const int32_t* __restrict__ offsets,
                                                       const int32_t* __restrict__ runs, const HitRec* __restrict__ tmp,
-                                                      HitRec* __restrict__ recs) {
-    const int2 b = blk[blockIdx.x];
-    const int32_t off = offsets[blockIdx.x] + runs[blockIdx.x / kScanRun];
-    for (int i = threadIdx.x; i < b.x; i += kThreads) {
-        const float4* src = reinterpret_cast<const float4*>(tmp + b.y + i);
-        float4* dst = reinterpret_cast<float4*>(recs + off + i);
-        dst[0] = src[0];
-        dst[1] = src[1];
+                                                      HitRec* __restrict__ recs, int n_groups, int stride) {
+    for (int k = 0; k < n_groups; ++k) {
+        const int j = k * stride + int(blockIdx.x);
+        const int2 b = blk[j];
+        const int32_t off = offsets[j] + runs[j / kScanRun];
+        for (int i = threadIdx.x; i < b.x; i += kThreads) {
+            const float4* src = reinterpret_cast<const float4*>(tmp + b.y + i);
+            float4* dst = reinterpret_cast<float4*>(recs + off + i);
+            dst[0] = src[0];
+            dst[1] = src[1];
+        }
     }
 }
 
@@ -573,8 +580,8 @@ struct TileElem<float> {
 // either is waited on.  Written as a recursion rather than a loop so that
 // every level index stays a compile-time constant (the features stay in
 // registers) at any level count.
-template <class TableT, int L, int LMAX, int F>
-__device__ __forceinline__ void gather_levels(const ModelC& m, float x, float y, float z, float (&e)[F]) {
+template <class TableT, int L, int LMAX, int F, class M>
+__device__ __forceinline__ void gather_levels(const M& m, float x, float y, float z, float (&e)[F]) {
     if constexpr (L < LMAX) {
         float2 ea = make_float2(0.f, 0.f), eb = make_float2(0.f, 0.f);
         if (L + 1 < m.n_levels) encode_level_pair<TableT>(m, m.lv[L], m.lv[L + 1], x, y, z, ea, eb);
@@ -602,78 +609,151 @@ struct ShadeShape {
     static constexpr size_t lds_bytes = size_t(weight_bytes(F, V, X)) + (kThreads / 64) * tile_bytes;
 };
 
-// Persistent waves over the packed hit list, 64 hits per wave step.  Each
-// lane gathers every level of its own hit (a level's loads then cover 64
-// neighbouring rays, and level parameters are wave-uniform), two levels at a
-// time so their offset loads are in flight together.  The network then runs
-// on four blocks of 16 rays; each block's features pass through the wave's
-// LDS tile into the matrix-core B-operand layout.
+// One wave step of the shading kernel: the records [base, base + 64) of
+// [.., n), one per lane.  Each lane gathers every level of its own hit (a
+// level's loads then cover 64 neighbouring rays, and level parameters are
+// wave-uniform), two levels at a time so their offset loads are in flight
+// together, and computes the SH values of its own ray.  The network then runs
+// on four blocks of 16 rays; each block's features and SH values pass
+// through the wave's LDS tile into the matrix-core B-operand layout.
 // NOLF (the paper's own i-NOLF form): the record's pad holds the ray's
 // coarse opacity, a further network input, and the colour buffer holds the
 // diffuse colour and tint of the hit, which the outputs complete as
 // (c_d + t c_s, alpha).
-template <class TableT, class P, int LPG, bool NOLF = false>
-__global__ __launch_bounds__(kThreads) INRF_MFMA_VGPR void k_shade(ModelC m, const HitRec* __restrict__ recs,
-                                                    const int32_t* __restrict__ first,
-                                                    const int32_t* __restrict__ counter, float* __restrict__ rgba) {
+template <class TableT, class P, int LPG, bool NOLF, class M>
+__device__ __forceinline__ void shade_step(const M& m, const typename Mfma<P>::vec* W,
+                                           typename TileElem<P>::type* tile, const HitRec* __restrict__ recs,
+                                           int64_t base, int64_t n, float* __restrict__ rgba) {
     constexpr int X = NOLF ? 1 : 0;
-    typedef Mfma<P> M;
-    typedef typename M::vec Vec;
+    typedef Mfma<P> Mf;
+    typedef typename Mf::vec Vec;
     typedef ShadeShape<P, LPG, X> S;
     typedef typename TileElem<P>::type T;
+    const int lane = __lane_id(), g = lane >> 4, r = lane & 15;
+    const int64_t i = base + lane;
+    const bool act = i < n;
+    HitRec h;
+    if (act) h = recs[i];
+    else h = HitRec{0.f, 0.f, 0.f, 0, 0.f, 0.f, 1.f, 0};
+    float e[S::F];
+#pragma unroll
+    for (int k = 2 * S::LMAX; k < S::F; ++k) e[k] = 0.f;
+    gather_levels<TableT, 0, S::LMAX>(m, h.x, h.y, h.z, e);
+    float sh[INRF_SH_DIM];  // of the lane's own ray (unit direction)
+    sh16(h.dx, h.dy, h.dz, sh);
+    const int nb = int(min<int64_t>(4, (n - base + 15) / 16));
+    for (int b = 0; b < nb; ++b) {
+        if (g == b) {
+            T* row = tile + r * S::STRIDE;
+#pragma unroll
+            for (int k = 0; k < S::F; ++k) row[k] = T(e[k]);
+#pragma unroll
+            for (int k = 0; k < INRF_SH_DIM; ++k) row[S::F + k] = T(sh[k]);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int src = 16 * b + r;
+        Vec b1[S::S1];
+        const float extra = NOLF ? __shfl(__int_as_float(h.pad), src) : 0.f;
+        load_inputs_row<P, S::F, X>(tile + r * S::STRIDE, b1, extra);
+        const int out = __shfl(h.out, src);
+        const f32x4 o = mlp_block<P, S::F, X>(W, b1);
+        if (g == 0 && base + src < n) {
+            float4* px = reinterpret_cast<float4*>(rgba) + out;
+            if constexpr (NOLF) {
+                const float4 dt = *px;  // diffuse RGB and tint
+                *px = make_float4(dt.x + dt.w * sigmoidf(o[0]), dt.y + dt.w * sigmoidf(o[1]),
+                                  dt.z + dt.w * sigmoidf(o[2]), sigmoidf(o[3]));
+            } else {
+                *px = make_float4(sigmoidf(o[0]), sigmoidf(o[1]), sigmoidf(o[2]), sigmoidf(o[3]));
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();  // the tile is rewritten by the next block
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// Persistent waves over the packed hit list [first, counter), 64 hits per
+// wave step (shade_step).
+template <class TableT, class P, int LPG, bool NOLF = false>
+__global__ __launch_bounds__(kThreads) INRF_MFMA_VGPR void k_shade(ModelC m, const HitRec* __restrict__ recs,
+                                                                   const int32_t* __restrict__ first,
+                                                                   const int32_t* __restrict__ counter,
+                                                                   float* __restrict__ rgba) {
+    constexpr int X = NOLF ? 1 : 0;
+    typedef typename Mfma<P>::vec Vec;
+    typedef ShadeShape<P, LPG, X> S;
+    typedef typename TileElem<P>::type T;
+    const int lo = first ? *first : 0, n = *counter;  // records [lo, n)
+    // a workgroup with no records to shade (few hits: a small frame) leaves
+    // before staging the weights
+    if (lo + int64_t(blockIdx.x) * kThreads >= n) return;
     extern __shared__ float4 lds_v[];
     Vec* W = reinterpret_cast<Vec*>(lds_v);
     stage_weights<P, X>(m.weights, m.n_levels, S::F, W);
     T* tile = reinterpret_cast<T*>(reinterpret_cast<char*>(lds_v) + weight_bytes(S::F, S::V, X) +
                                    (threadIdx.x / 64) * S::tile_bytes);
     __syncthreads();
-    const int lo = first ? *first : 0, n = *counter;  // records [lo, n)
-    const int lane = __lane_id(), g = lane >> 4, r = lane & 15;
     for (int64_t base = lo + (int64_t(blockIdx.x) * (kThreads / 64) + threadIdx.x / 64) * 64; base < n;
-         base += int64_t(gridDim.x) * kThreads) {
-        const int64_t i = base + lane;
-        const bool act = i < n;
-        HitRec h;
-        if (act) h = recs[i];
-        else h = HitRec{0.f, 0.f, 0.f, 0, 0.f, 0.f, 1.f, 0};
-        float e[S::F];
-#pragma unroll
-        for (int k = 2 * S::LMAX; k < S::F; ++k) e[k] = 0.f;
-        gather_levels<TableT, 0, S::LMAX>(m, h.x, h.y, h.z, e);
-        float sh[INRF_SH_DIM];  // of the lane's own ray (unit direction)
-        sh16(h.dx, h.dy, h.dz, sh);
-        const int nb = int(min<int64_t>(4, (int64_t(n) - base + 15) / 16));
-        for (int b = 0; b < nb; ++b) {
-            if (g == b) {
-                T* row = tile + r * S::STRIDE;
-#pragma unroll
-                for (int k = 0; k < S::F; ++k) row[k] = T(e[k]);
-#pragma unroll
-                for (int k = 0; k < INRF_SH_DIM; ++k) row[S::F + k] = T(sh[k]);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const int src = 16 * b + r;
-            Vec b1[S::S1];
-            const float extra = NOLF ? __shfl(__int_as_float(h.pad), src) : 0.f;
-            load_inputs_row<P, S::F, X>(tile + r * S::STRIDE, b1, extra);
-            const int out = __shfl(h.out, src);
-            const f32x4 o = mlp_block<P, S::F, X>(W, b1);
-            if (g == 0 && base + src < n) {
-                float4* px = reinterpret_cast<float4*>(rgba) + out;
-                if constexpr (NOLF) {
-                    const float4 dt = *px;  // diffuse RGB and tint
-                    *px = make_float4(dt.x + dt.w * sigmoidf(o[0]), dt.y + dt.w * sigmoidf(o[1]),
-                                      dt.z + dt.w * sigmoidf(o[2]), sigmoidf(o[3]));
-                } else {
-                    *px = make_float4(sigmoidf(o[0]), sigmoidf(o[1]), sigmoidf(o[2]), sigmoidf(o[3]));
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();  // the tile is rewritten by the next block
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+         base += int64_t(gridDim.x) * kThreads)
+        shade_step<TableT, P, LPG, NOLF>(m, W, tile, recs, base, n, rgba);
+}
+
+// The shading view of one object of a scene: its tables, weights and level
+// parameters (at most 16 levels), small enough that a whole scene's set
+// travels as one kernel argument.
+struct ShadeModel {
+    int32_t n_levels, pad;
+    const uint32_t* phi;
+    const void* table;
+    const float* weights;
+    LevelC lv[16];
+};
+struct ShadeSet {
+    int32_t n, pad;
+    ShadeModel m[INRF_MAX_OBJECTS];
+};
+
+// Every object of a scene in one launch.  The packed records are grouped by
+// object (object o's records are [seg[o], seg[o+1])); each object's run is
+// cut into chunks of one workgroup step (256 records), and workgroup b takes
+// a contiguous share of the chunks of all objects in order, restaging the
+// weights in LDS when its chunk's object changes.  All objects share the
+// table type and precision; LPG covers the largest level count.
+template <class TableT, class P, int LPG>
+__global__ __launch_bounds__(kThreads) INRF_MFMA_VGPR void k_shade_scene(ShadeSet ss, const HitRec* __restrict__ recs,
+                                                                         const int32_t* __restrict__ seg,
+                                                                         float* __restrict__ rgba) {
+    typedef typename Mfma<P>::vec Vec;
+    typedef ShadeShape<P, LPG> S;
+    typedef typename TileElem<P>::type T;
+    // chunks per object and in all (the same sums in every workgroup)
+    int total = 0;
+    for (int o = 0; o < ss.n; ++o) total += (seg[o + 1] - seg[o] + kThreads - 1) / kThreads;
+    const int c0 = int(int64_t(total) * blockIdx.x / gridDim.x), c1 = int(int64_t(total) * (blockIdx.x + 1) / gridDim.x);
+    if (c0 >= c1) return;
+    extern __shared__ float4 lds_v[];
+    Vec* W = reinterpret_cast<Vec*>(lds_v);
+    T* tile = reinterpret_cast<T*>(reinterpret_cast<char*>(lds_v) + weight_bytes(S::F, S::V) +
+                                   (threadIdx.x / 64) * S::tile_bytes);
+    int staged = -1, o = 0, first_chunk = 0;  // object of chunk c: first_chunk <= c < first_chunk + its chunks
+    for (int c = c0; c < c1; ++c) {
+        while (c >= first_chunk + (seg[o + 1] - seg[o] + kThreads - 1) / kThreads) {
+            first_chunk += (seg[o + 1] - seg[o] + kThreads - 1) / kThreads;
+            ++o;
         }
+        const int obj = __builtin_amdgcn_readfirstlane(o);
+        if (obj != staged) {
+            __syncthreads();  // every wave is done with the previous object's weights
+            stage_weights<P>(ss.m[obj].weights, ss.m[obj].n_levels, S::F, W);
+            __syncthreads();
+            staged = obj;
+        }
+        const int64_t base = seg[obj] + int64_t(c - first_chunk) * kThreads + (threadIdx.x / 64) * 64;
+        const int64_t n = seg[obj + 1];
+        if (base < n) shade_step<TableT, P, LPG, false>(ss.m[obj], W, tile, recs, base, n, rgba);
     }
 }
 
@@ -1163,6 +1243,35 @@ void launch_shade(const ModelC& c, int32_t precision, const HitRec* recs, const 
 #undef INRF_SHADE
 }
 
+// Every object of a scene in one shading launch (k_shade_scene); the
+// objects share the table type, and LPG covers the largest level count.
+template <class TableT, class P, int LPG>
+void launch_shade_scene_t(const ShadeSet& ss, const HitRec* recs, const int32_t* seg, float* rgba, hipStream_t s) {
+    const size_t lds = ShadeShape<P, LPG>::lds_bytes;
+    auto kern = k_shade_scene<TableT, P, LPG>;
+    hipLaunchKernelGGL(kern, dim3(resident_grid(kern, lds)), dim3(kThreads), lds, s, ss, recs, seg, rgba);
+}
+
+template <class TableT>
+void launch_shade_scene(const ShadeSet& ss, int max_levels, int32_t precision, const HitRec* recs, const int32_t* seg,
+                        float* rgba, hipStream_t s) {
+#define INRF_SHADE_SCENE(LPG)                                                                        \
+    do {                                                                                            \
+        if (precision == INRF_PREC_FP32) launch_shade_scene_t<TableT, float, LPG>(ss, recs, seg, rgba, s); \
+        else if (precision == INRF_PREC_FP16)                                                       \
+            launch_shade_scene_t<TableT, _Float16, LPG>(ss, recs, seg, rgba, s);                    \
+        else launch_shade_scene_t<TableT, __bf16, LPG>(ss, recs, seg, rgba, s);                     \
+    } while (0)
+    switch ((max_levels + 3) / 4) {
+        case 1: INRF_SHADE_SCENE(1); break;
+        case 2: INRF_SHADE_SCENE(2); break;
+        case 3: INRF_SHADE_SCENE(3); break;
+        case 4: INRF_SHADE_SCENE(4); break;
+        default: fail(INRF_E_UNSUPPORTED, "level count");
+    }
+#undef INRF_SHADE_SCENE
+}
+
 void check_precision(int32_t p) {
     require(p == INRF_PREC_FP32 || p == INRF_PREC_FP16 || p == INRF_PREC_BF16, "unknown precision");
 }
@@ -1289,7 +1398,7 @@ void trace_to_hits(const ModelC& c, const CamSet<NCAM>* cams, const float* ray_o
     hipLaunchKernelGGL(k_scan_runs, dim3(1), dim3(kScanThreads), 0, s, runs, n_runs, counter, counter + 1,
                        kMaxChunks - 1);
     launch_check("k_scan_runs");
-    hipLaunchKernelGGL(k_compact, dim3(n_blk), dim3(kThreads), 0, s, blk, offsets, runs, a.tmp, recs);
+    hipLaunchKernelGGL(k_compact, dim3(n_blk), dim3(kThreads), 0, s, blk, offsets, runs, a.tmp, recs, 1, n_blk);
     launch_check("k_compact");
 }
 
@@ -1531,10 +1640,36 @@ void run_scene(const inrf_instance* objects, int32_t n_objs, int32_t precision, 
     hipLaunchKernelGGL(k_scan_runs, dim3(1), dim3(kScanThreads), 0, s, runs, n_runs, counter, counter + 1,
                        kMaxChunks - 1);
     launch_check("k_scan_runs");
-    hipLaunchKernelGGL(k_compact, dim3(n_blk), dim3(kThreads), 0, s, blk, offsets, runs, a.tmp, recs);
+    hipLaunchKernelGGL(k_compact, dim3(n_tiles), dim3(kThreads), 0, s, blk, offsets, runs, a.tmp, recs, n_objs, n_tiles);
     launch_check("k_compact");
     hipLaunchKernelGGL(k_segments, dim3(1), dim3(64), 0, s, offsets, runs, n_tiles, n_objs, counter, seg);
     launch_check("k_segments");
+    // one shading launch for all objects when they share the table type and
+    // have at most 16 levels (the kernel argument's level tables), else one
+    // launch per object over its run of records
+    bool together = true;
+    int max_levels = 1;
+    for (int k = 0; k < n_objs; ++k) {
+        together = together && models[size_t(k)].n_levels <= 16 && models[size_t(k)].table_dtype == models[0].table_dtype;
+        max_levels = std::max(max_levels, int(models[size_t(k)].n_levels));
+    }
+    if (together) {
+        ShadeSet ss;
+        std::memset(&ss, 0, sizeof(ss));
+        ss.n = n_objs;
+        for (int k = 0; k < n_objs; ++k) {
+            const ModelC& c = models[size_t(k)];
+            ss.m[k].n_levels = c.n_levels;
+            ss.m[k].phi = c.phi;
+            ss.m[k].table = c.table;
+            ss.m[k].weights = c.weights;
+            for (int l = 0; l < c.n_levels; ++l) ss.m[k].lv[l] = c.lv[l];
+        }
+        if (models[0].table_dtype == INRF_F32) launch_shade_scene<float>(ss, max_levels, precision, recs, seg, rgba, s);
+        else launch_shade_scene<__half>(ss, max_levels, precision, recs, seg, rgba, s);
+        launch_check("k_shade_scene");
+        return;
+    }
     for (int k = 0; k < n_objs; ++k) {
         const ModelC& c = models[size_t(k)];
         if (c.table_dtype == INRF_F32) launch_shade<float>(c, precision, recs, seg + k, seg + k + 1, rgba, s);
@@ -1643,7 +1778,7 @@ void run_nolf(const inrf_model* m, const inrf_cubes* cubes, int32_t precision, c
     hipLaunchKernelGGL(k_scan_runs, dim3(1), dim3(kScanThreads), 0, s, runs, n_runs, counter, counter + 1,
                        kMaxChunks - 1);
     launch_check("k_scan_runs");
-    hipLaunchKernelGGL(k_compact, dim3(n_blk), dim3(kThreads), 0, s, blk, offsets, runs, a.tmp, recs);
+    hipLaunchKernelGGL(k_compact, dim3(n_blk), dim3(kThreads), 0, s, blk, offsets, runs, a.tmp, recs, 1, n_blk);
     launch_check("k_compact");
     if (c.table_dtype == INRF_F32) launch_shade_nolf<float>(c, precision, recs, counter, rgba, s);
     else launch_shade_nolf<__half>(c, precision, recs, counter, rgba, s);
