@@ -719,9 +719,13 @@ struct ShadeSet {
 // Every object of a scene in one launch.  The packed records are grouped by
 // object (object o's records are [seg[o], seg[o+1])); each object's run is
 // cut into chunks of one workgroup step (256 records), and workgroup b takes
-// a contiguous share of the chunks of all objects in order, restaging the
-// weights in LDS when its chunk's object changes.  All objects share the
-// table type and precision; LPG covers the largest level count.
+// chunks b, b + G, b + 2G, ... (G workgroups) of all objects in order, so the
+// rays in flight at any moment are neighbours in the list, as in k_shade.
+// A workgroup restages the weights in LDS when its chunk's object changes.
+// All objects share the table type and precision; LPG covers the largest
+// level count.  (Measured against giving each object its own share of the
+// workgroups, staged once: slower, 0.97 against 0.92 ms for the 12-object
+// 4K frame.)
 template <class TableT, class P, int LPG>
 __global__ __launch_bounds__(kThreads) INRF_MFMA_VGPR void k_shade_scene(ShadeSet ss, const HitRec* __restrict__ recs,
                                                                          const int32_t* __restrict__ seg,
@@ -732,14 +736,13 @@ __global__ __launch_bounds__(kThreads) INRF_MFMA_VGPR void k_shade_scene(ShadeSe
     // chunks per object and in all (the same sums in every workgroup)
     int total = 0;
     for (int o = 0; o < ss.n; ++o) total += (seg[o + 1] - seg[o] + kThreads - 1) / kThreads;
-    const int c0 = int(int64_t(total) * blockIdx.x / gridDim.x), c1 = int(int64_t(total) * (blockIdx.x + 1) / gridDim.x);
-    if (c0 >= c1) return;
+    if (int(blockIdx.x) >= total) return;
     extern __shared__ float4 lds_v[];
     Vec* W = reinterpret_cast<Vec*>(lds_v);
     T* tile = reinterpret_cast<T*>(reinterpret_cast<char*>(lds_v) + weight_bytes(S::F, S::V) +
                                    (threadIdx.x / 64) * S::tile_bytes);
     int staged = -1, o = 0, first_chunk = 0;  // object of chunk c: first_chunk <= c < first_chunk + its chunks
-    for (int c = c0; c < c1; ++c) {
+    for (int c = blockIdx.x; c < total; c += gridDim.x) {
         while (c >= first_chunk + (seg[o + 1] - seg[o] + kThreads - 1) / kThreads) {
             first_chunk += (seg[o + 1] - seg[o] + kThreads - 1) / kThreads;
             ++o;
