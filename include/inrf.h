@@ -468,12 +468,17 @@ inrf_status inrf_backward(const inrf_model* m, const float* ray_o, const float* 
  *   param -= lr * (m / (1 - beta1^step)) / (sqrt(v / (1 - beta2^step)) + eps).
  * With zero_grad set, g is cleared after use.  param_f16 (nullable, device
  * half [n]) receives the updated parameters rounded to FP16, e.g. the FP16
- * feature table the reduced-precision render reads. */
+ * feature table the reduced-precision render reads.  With lazy set, only
+ * parameters whose g is nonzero are stepped (and cleared, and copied to
+ * param_f16); the others keep their value and moments, so a step over a
+ * table of which a batch touched a small part reads g everywhere but param,
+ * m and v only where g is nonzero (sparse or "lazy" Adam; step is still the
+ * global step count). */
 typedef struct inrf_adam_params {
     float lr, beta1, beta2, eps;
     int64_t step;      /* t >= 1 */
     int32_t zero_grad; /* nonzero: clear grad */
-    int32_t pad;
+    int32_t lazy;      /* nonzero: step only parameters with a nonzero gradient */
 } inrf_adam_params;
 
 inrf_status inrf_adam(float* param, float* grad, float* m, float* v, int64_t n, const inrf_adam_params* p,

@@ -80,7 +80,7 @@ class CubesDesc(ctypes.Structure):
 
 class AdamParams(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
-                ("eps", ctypes.c_float), ("step", c_int64), ("zero_grad", c_int32), ("pad", c_int32)]
+                ("eps", ctypes.c_float), ("step", c_int64), ("zero_grad", c_int32), ("lazy", c_int32)]
 
 
 _lib = None

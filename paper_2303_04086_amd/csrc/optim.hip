@@ -3,6 +3,10 @@
 // streaming kernel: per parameter it reads param, grad, m, v and writes
 // param, m, v (and optionally an FP16 copy, and a cleared grad), so it runs
 // at HBM bandwidth; four parameters per lane with 16-byte accesses.
+// Lazy mode updates only parameters with a nonzero gradient (value and
+// moments of the others stay as they are): a batch touches the table slots
+// around its rays' hit points, a small part of the table, and the step then
+// reads the gradient everywhere but param, m and v only where it is nonzero.
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 
@@ -19,7 +23,7 @@ namespace dev {
 struct AdamC {
     float lr, beta1, beta2, eps;
     float inv_bias1, inv_sqrt_bias2;  // 1 / (1 - beta1^t), 1 / sqrt(1 - beta2^t)
-    int32_t zero_grad;
+    int32_t zero_grad, lazy;
 };
 
 __device__ __forceinline__ float adam_one(float& p, float g, float& m, float& v, const AdamC& a) {
@@ -34,14 +38,17 @@ __global__ void k_adam(float* __restrict__ param, float* __restrict__ grad, floa
     const int64_t n4 = n / 4;
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n4; i += stride) {
-        float4 p = reinterpret_cast<float4*>(param)[i];
         const float4 g = reinterpret_cast<const float4*>(grad)[i];
+        const bool ux = !a.lazy || g.x != 0.f, uy = !a.lazy || g.y != 0.f, uz = !a.lazy || g.z != 0.f,
+                   uw = !a.lazy || g.w != 0.f;
+        if (!(ux || uy || uz || uw)) continue;  // lazy: nothing to update, nothing to clear
+        float4 p = reinterpret_cast<float4*>(param)[i];
         float4 m = reinterpret_cast<float4*>(mom)[i];
         float4 v = reinterpret_cast<float4*>(vel)[i];
-        adam_one(p.x, g.x, m.x, v.x, a);
-        adam_one(p.y, g.y, m.y, v.y, a);
-        adam_one(p.z, g.z, m.z, v.z, a);
-        adam_one(p.w, g.w, m.w, v.w, a);
+        if (ux) adam_one(p.x, g.x, m.x, v.x, a);
+        if (uy) adam_one(p.y, g.y, m.y, v.y, a);
+        if (uz) adam_one(p.z, g.z, m.z, v.z, a);
+        if (uw) adam_one(p.w, g.w, m.w, v.w, a);
         reinterpret_cast<float4*>(param)[i] = p;
         reinterpret_cast<float4*>(mom)[i] = m;
         reinterpret_cast<float4*>(vel)[i] = v;
@@ -53,7 +60,7 @@ __global__ void k_adam(float* __restrict__ param, float* __restrict__ grad, floa
     }
     // tail of n % 4 elements
     const int64_t k = 4 * n4 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (k < n) {
+    if (k < n && (!a.lazy || grad[k] != 0.f)) {
         float p = param[k], m = mom[k], v = vel[k];
         adam_one(p, grad[k], m, v, a);
         param[k] = p;
@@ -91,6 +98,7 @@ extern "C" inrf_status inrf_adam(float* param, float* grad, float* m, float* v, 
         a.inv_bias1 = float(1.0 / (1.0 - std::pow(double(p->beta1), double(p->step))));
         a.inv_sqrt_bias2 = float(1.0 / std::sqrt(1.0 - std::pow(double(p->beta2), double(p->step))));
         a.zero_grad = p->zero_grad;
+        a.lazy = p->lazy;
         const int64_t n4 = n / 4;
         const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n4 + 255) / 256, 8192));
         hipLaunchKernelGGL(dev::k_adam, dim3(unsigned(blocks)), dim3(256), 0, reinterpret_cast<hipStream_t>(stream),

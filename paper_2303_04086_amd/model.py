@@ -590,10 +590,10 @@ class FramePipeline:
 
 
 def adam_step(param, grad, m, v, step: int, lr: float = 1e-2, beta1: float = 0.9, beta2: float = 0.99,
-              eps: float = 1e-15, zero_grad: bool = True, param_f16=None, stream=None):
+              eps: float = 1e-15, zero_grad: bool = True, param_f16=None, stream=None, lazy: bool = False):
     """One Adam step in place on contiguous float32 device tensors of equal
     size (the library's k_adam); param_f16, if given, receives the updated
-    parameters in FP16."""
+    parameters in FP16.  lazy: step only parameters with a nonzero gradient."""
     import torch
     n = param.numel()
     for t in (grad, m, v):
@@ -603,6 +603,7 @@ def adam_step(param, grad, m, v, step: int, lr: float = 1e-2, beta1: float = 0.9
         raise ValueError("param_f16 must be a float16 tensor of param's size")
     p = L.AdamParams()
     p.lr, p.beta1, p.beta2, p.eps, p.step, p.zero_grad = lr, beta1, beta2, eps, int(step), int(bool(zero_grad))
+    p.lazy = int(bool(lazy))
     s = stream if stream is not None else torch.cuda.current_stream(param.device)
     L.check(L.lib().inrf_adam(L.ptr(param), L.ptr(grad), L.ptr(m), L.ptr(v), n, ctypes.byref(p), L.ptr(param_f16),
                               ctypes.c_void_p(s.cuda_stream)))

@@ -60,11 +60,15 @@ class Trainer:
     """Adam (lr 1e-2, betas 0.9 / 0.99 by default) on a Renderer's FP32
     master table and weights, minimising the mean over rays of the squared
     RGBA error.  Gradients accumulate in persistent buffers that the Adam
-    kernel clears; a resident FP16 table is refreshed by every step."""
+    kernel clears; a resident FP16 table is refreshed by every step.
+    lazy_table: step only the table entries the batch gave a nonzero
+    gradient (the weights always take a dense step)."""
 
-    def __init__(self, R: Renderer, lr: float = 1e-2, beta1: float = 0.9, beta2: float = 0.99, eps: float = 1e-15):
+    def __init__(self, R: Renderer, lr: float = 1e-2, beta1: float = 0.9, beta2: float = 0.99, eps: float = 1e-15,
+                 lazy_table: bool = False):
         torch = _torch()
         self.R, self.lr, self.beta1, self.beta2, self.eps = R, lr, beta1, beta2, eps
+        self.lazy_table = bool(lazy_table)
         t, w = R.tables["f32"], R.weights
         self.g_table, self.m_table, self.v_table = (torch.zeros_like(t) for _ in range(3))
         self.g_w, self.m_w, self.v_w = (torch.zeros_like(w) for _ in range(3))
@@ -82,6 +86,7 @@ class Trainer:
         self.t += 1
         kw = dict(lr=self.lr, beta1=self.beta1, beta2=self.beta2, eps=self.eps, zero_grad=True)
         adam_step(R.tables["f32"].view(-1), self.g_table.view(-1), self.m_table.view(-1), self.v_table.view(-1),
-                  self.t, param_f16=R.tables["f16"].view(-1) if "f16" in R.tables else None, **kw)
+                  self.t, param_f16=R.tables["f16"].view(-1) if "f16" in R.tables else None, lazy=self.lazy_table,
+                  **kw)
         adam_step(R.weights, self.g_w, self.m_w, self.v_w, self.t, **kw)
         return loss

@@ -230,6 +230,34 @@ def test_adam_matches_oracle(n):
         adam_step(tp, tg, tm, tv, 0)
 
 
+@pytest.mark.parametrize("n", [4099, 1 << 16])
+def test_adam_lazy_matches_oracle(n):
+    """Lazy Adam: entries with a zero gradient keep value, moments and FP16
+    copy; the others match the FP64 lazy step."""
+    from paper_2303_04086_amd.model import adam_step
+    rng = np.random.default_rng(n + 1)
+    p = rng.normal(size=n).astype(np.float32)
+    m = (0.1 * rng.normal(size=n)).astype(np.float32)
+    v = np.abs(0.1 * rng.normal(size=n)).astype(np.float32)
+    tp, tm, tv = _dev(p), _dev(m), _dev(v)
+    half = tp.to(torch.float16)
+    rp, rm, rv = p.astype(np.float64), m.astype(np.float64), v.astype(np.float64)
+    for t in range(1, 4):
+        g = rng.normal(size=n).astype(np.float32)
+        g[rng.random(n) < 0.6] = 0.0
+        g[:8] = 0.0  # a whole 4-group of zeros (skipped), and a ragged tail below
+        g[-3:] = [0.0, 1.5, 0.0]
+        tg = _dev(g)
+        adam_step(tp, tg, tm, tv, t, lr=1e-2, beta1=0.9, beta2=0.99, eps=1e-15, param_f16=half, lazy=True)
+        rp, rm, rv = oracle.adam_step(rp, g, rm, rv, t, 1e-2, 0.9, 0.99, 1e-15, lazy=True)
+        torch.cuda.synchronize()
+        assert torch.count_nonzero(tg).item() == 0
+        assert np.abs(tp.cpu().numpy() - rp).max() <= 1e-6
+        assert np.abs(tm.cpu().numpy() - rm).max() <= 1e-6 and np.abs(tv.cpu().numpy() - rv).max() <= 1e-6
+        assert torch.equal(half, tp.to(torch.float16))
+    assert np.array_equal(tp.cpu().numpy()[:8], p[:8]) and np.array_equal(tm.cpu().numpy()[:8], m[:8])
+
+
 def test_backward_rejects_more_than_16_levels():
     import paper_2303_04086_amd as P
     w = synth.workload_tiny()

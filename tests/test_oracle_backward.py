@@ -110,6 +110,27 @@ def test_adam_first_step_is_normalised_gradient():
     assert np.allclose(m1, 0.1 * g) and np.allclose(v1, 0.01 * g * g)
 
 
+def test_adam_lazy_skips_zero_gradients():
+    """Lazy (sparse) Adam: a zero gradient leaves value and moments as they
+    are even with nonzero moments (a dense step would move both), and a
+    nonzero gradient from zero moments at t = 1 gives the closed-form step
+    lr * g / (|g| + eps)."""
+    p = np.array([1.0, -2.0, 0.5, 3.0])
+    m = np.array([0.5, 0.0, -0.25, 0.0])
+    v = np.array([0.25, 0.0, 0.5, 0.0])
+    g = np.array([0.0, 2.0, 0.0, -0.5])
+    lr, eps = 1e-2, 1e-15
+    p1, m1, v1 = oracle.adam_step(p, g, m, v, 1, lr, 0.9, 0.99, eps, lazy=True)
+    assert p1[0] == 1.0 and m1[0] == 0.5 and v1[0] == 0.25
+    assert p1[2] == 0.5 and m1[2] == -0.25 and v1[2] == 0.5
+    assert np.isclose(p1[1], -2.0 - lr * 2.0 / (2.0 + eps), rtol=1e-14)
+    assert np.isclose(p1[3], 3.0 + lr * 0.5 / (0.5 + eps), rtol=1e-14)
+    assert np.isclose(m1[1], 0.2) and np.isclose(v1[3], 0.01 * 0.25)
+    # the dense step moves the zero-gradient entries: by -lr * m_hat / (sqrt(v_hat) + eps)
+    q, _, _ = oracle.adam_step(p, g, m, v, 1, lr, 0.9, 0.99, eps)
+    assert np.isclose(q[0], 1.0 - lr * (0.45 / 0.1) / (np.sqrt(0.99 * 0.25 / 0.01) + eps), rtol=1e-12)
+
+
 def test_adam_constant_gradient_keeps_step():
     g = np.array([0.3, -2.0, 1e-3])
     p, m, v = np.zeros(3), np.zeros(3), np.zeros(3)
