@@ -542,13 +542,19 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_runs(int32_t* __restrict_
 __global__ __launch_bounds__(kThreads) void k_compact(const int2* __restrict__ blk, const int32_t* __restrict__ offsets,
                                                       const int32_t* __restrict__ runs, const HitRec* __restrict__ tmp,
                                                       HitRec* __restrict__ recs, int n_groups, int stride) {
-    for (int k = 0; k < n_groups; ++k) {
-        const int j = k * stride + int(blockIdx.x);
+    // the runs' (count, source) and destinations, all requested at once (n_groups <= kThreads)
+    __shared__ int3 s_run[kThreads];
+    if (int(threadIdx.x) < n_groups) {
+        const int j = int(threadIdx.x) * stride + int(blockIdx.x);
         const int2 b = blk[j];
-        const int32_t off = offsets[j] + runs[j / kScanRun];
-        for (int i = threadIdx.x; i < b.x; i += kThreads) {
-            const float4* src = reinterpret_cast<const float4*>(tmp + b.y + i);
-            float4* dst = reinterpret_cast<float4*>(recs + off + i);
+        s_run[threadIdx.x] = make_int3(b.x, b.y, offsets[j] + runs[j / kScanRun]);
+    }
+    __syncthreads();
+    for (int k = 0; k < n_groups; ++k) {
+        const int3 r = s_run[k];
+        for (int i = threadIdx.x; i < r.x; i += kThreads) {
+            const float4* src = reinterpret_cast<const float4*>(tmp + r.y + i);
+            float4* dst = reinterpret_cast<float4*>(recs + r.z + i);
             dst[0] = src[0];
             dst[1] = src[1];
         }
