@@ -764,6 +764,7 @@ def main():
     targets = {"gather_ge_0.60_of_hbm": {"value": roof["frac"], "met": bool(roof["frac"] >= 0.60)}}
     if mlp:
         targets["mlp_ge_0.40_of_mfma"] = {"value": mlp["fp16"]["utilisation"],
+                                          "of_measured_peak": mlp["fp16"].get("utilisation_of_measured_peak"),
                                           "met": bool(mlp["fp16"]["utilisation"] >= 0.40)}
     if errors:
         targets["fp32_max_abs_le_1e-5"] = {"value": errors["fp32"]["max_abs_not_grazing"],
