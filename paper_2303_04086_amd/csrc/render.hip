@@ -564,10 +564,15 @@ __global__ __launch_bounds__(kThreads) void k_compact(const int2* __restrict__ b
 // ------------------------------------------------------------- shading ----
 
 // Network kernels are declared to fit in at most 256 registers per lane (at
-// least two waves per SIMD), which they do anyway; with that bound the
+// least two waves per SIMD), which those of up to 16 levels do anyway (the
+// shading kernel's larger instantiations keep the full register file, as they
+// would spill in 256); with that bound the
 // compiler keeps matrix-instruction results in ordinary vector registers
 // instead of accumulation registers that must be copied out before the
-// ReLU and the next layer.
+// ReLU and the next layer.  (k_mlp on FP32 rows keeps the accumulation
+// registers: in vector registers its 20- to 32-level instantiations were
+// given a destination partially overlapping the accumulator input, which the
+// build's assembly check refuses.)
 #ifndef INRF_MFMA_VGPR
 #define INRF_MFMA_VGPR __attribute__((amdgpu_waves_per_eu(2)))
 #endif
@@ -684,7 +689,8 @@ __device__ __forceinline__ void shade_step(const M& m, const typename Mfma<P>::v
 // Persistent waves over the packed hit list [first, counter), 64 hits per
 // wave step (shade_step).
 template <class TableT, class P, int LPG, bool NOLF = false>
-__global__ __launch_bounds__(kThreads) INRF_MFMA_VGPR void k_shade(ModelC m, const HitRec* __restrict__ recs,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(LPG <= 4 ? 2 : 1)))
+void k_shade(ModelC m, const HitRec* __restrict__ recs,
                                                                    const int32_t* __restrict__ first,
                                                                    const int32_t* __restrict__ counter,
                                                                    float* __restrict__ rgba) {
@@ -708,14 +714,15 @@ __global__ __launch_bounds__(kThreads) INRF_MFMA_VGPR void k_shade(ModelC m, con
 }
 
 // The shading view of one object of a scene: its tables, weights and level
-// parameters (at most 16 levels), small enough that a whole scene's set
+// parameters (at most 12 levels), small enough that a whole scene's set
 // travels as one kernel argument.
+constexpr int kSceneShadeLevels = 12;
 struct ShadeModel {
     int32_t n_levels, pad;
     const uint32_t* phi;
     const void* table;
     const float* weights;
-    LevelC lv[16];
+    LevelC lv[kSceneShadeLevels];
 };
 struct ShadeSet {
     int32_t n, pad;
@@ -816,7 +823,7 @@ __device__ __forceinline__ f32x4 load_inputs4(const float* a, int k, int limit, 
 // The network alone on caller inputs [n][d_in] in natural order: lane
 // (g, r) loads exactly its B operands of ray r straight from memory.
 template <class P, int LPG>
-__global__ __launch_bounds__(kThreads) INRF_MFMA_VGPR void k_mlp(ModelC m, const float* __restrict__ x, int64_t n,
+__global__ __launch_bounds__(kThreads) void k_mlp(ModelC m, const float* __restrict__ x, int64_t n,
                                                   float* __restrict__ rgba, bool vec) {
     typedef Mfma<P> M;
     typedef typename M::vec Vec;
@@ -1275,7 +1282,6 @@ void launch_shade_scene(const ShadeSet& ss, int max_levels, int32_t precision, c
         case 1: INRF_SHADE_SCENE(1); break;
         case 2: INRF_SHADE_SCENE(2); break;
         case 3: INRF_SHADE_SCENE(3); break;
-        case 4: INRF_SHADE_SCENE(4); break;
         default: fail(INRF_E_UNSUPPORTED, "level count");
     }
 #undef INRF_SHADE_SCENE
@@ -1654,12 +1660,13 @@ void run_scene(const inrf_instance* objects, int32_t n_objs, int32_t precision, 
     hipLaunchKernelGGL(k_segments, dim3(1), dim3(64), 0, s, offsets, runs, n_tiles, n_objs, counter, seg);
     launch_check("k_segments");
     // one shading launch for all objects when they share the table type and
-    // have at most 16 levels (the kernel argument's level tables), else one
+    // have at most 12 levels (the kernel argument's level tables), else one
     // launch per object over its run of records
     bool together = true;
     int max_levels = 1;
     for (int k = 0; k < n_objs; ++k) {
-        together = together && models[size_t(k)].n_levels <= 16 && models[size_t(k)].table_dtype == models[0].table_dtype;
+        together = together && models[size_t(k)].n_levels <= kSceneShadeLevels &&
+                   models[size_t(k)].table_dtype == models[0].table_dtype;
         max_levels = std::max(max_levels, int(models[size_t(k)].n_levels));
     }
     if (together) {
