@@ -16,8 +16,10 @@ batches are on the device at once, each on a stream (default priority)
 with its own workspace and output buffer, allocated once; a new batch is
 formed from the queue as soon as a slot frees up, so requests that arrive
 while others render are admitted as slots and memory free up, and their
-work overlaps on the device.  A request's latency is the host time at which
-its batch was seen complete minus its arrival time.
+work overlaps on the device.  With every slot busy the loop blocks on the
+oldest batch's event; otherwise it polls, yielding the core between polls.
+A request's latency is the host time at which its batch was seen complete
+minus its arrival time.
 """
 from __future__ import annotations
 
@@ -120,8 +122,13 @@ class Server:
                 pixels += pix
                 sizes.append(len(batch))
                 held.append(self.cost(len(batch), pix))
+            elif flight and not free:
+                # every slot is busy: nothing can start before the oldest batch completes
+                flight[0][2].synchronize()
             elif not flight and i < len(todo):
                 time.sleep(max(0.0, min(1e-3, todo[i].arrival_s * time_scale - now)))
+            else:
+                time.sleep(0)  # waiting on a completion or an arrival: yield the core between polls
         span = time.perf_counter() - t0
         return {"requests": len(lat), "batches": len(sizes), "mean_batch": round(sum(sizes) / max(1, len(sizes)), 2),
                 "in_flight": len(self.slots), "hbm_budget_bytes": self.budget,
