@@ -241,8 +241,9 @@ int64_t inrf_workspace_size(int64_t n_rays);
  * ws: device workspace of at least inrf_workspace_size(width*height) bytes;
  * its first two int32 receive the frame's hit-ray count and zero.  The
  * proxy's triangles are first sorted into lists per 8x8-pixel quadrant of
- * the frame (the workspace holds up to width*height list entries; a
- * quadrant whose list does not fit is traced through the BVH instead), and
+ * the frame (256 slots per quadrant, longer lists in a spill area of one
+ * entry per pixel; a quadrant whose list fits neither is traced through the
+ * BVH instead), and
  * every ray is tested against its quadrant's list: the closest hit (ties to
  * the lower triangle index) is the one inrf_forward finds on the same ray
  * through the BVH.  Everything is enqueued on `stream`. */
@@ -267,7 +268,7 @@ inrf_status inrf_render_profiled(const inrf_model* m, int32_t precision, const i
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation):
  * inrf_render without a workspace argument.  Its scratch memory is a static
- * device array of the library (74.5 MiB, held by each GPU the library
+ * device array of the library (75.9 MiB, held by each GPU the library
  * runs on until the process ends), so frames are limited to
  * INRF_STATIC_MAX_PIXELS pixels (INRF_E_SIZE beyond, nothing enqueued).
  * The call allocates nothing and creates no runtime object.  Every call on

@@ -22,9 +22,17 @@
 // the projection and of the ray directions is far below a pixel).  A
 // triangle whose vertices all have lambda <= -0.05 |q| lies behind the
 // camera and is never hit.  Any other triangle (crossing the camera plane)
-// goes into a global list that every quadrant tests.  A quadrant whose list
-// did not fit the workspace, or every quadrant when the global list
-// overflows, walks the BVH instead.
+// goes into a global list that every quadrant tests.
+//
+// Lists.  Each quadrant has kBinCap slots, filled in one pass (k_bin):
+// facing triangles from the start up, the others from the end down, each
+// side counted by its own atomic counter, which keeps counting past the
+// capacity.  The counts are therefore exact, and a quadrant whose two counts
+// add up to more than kBinCap (its two sides then overlap) gets a list of
+// exactly that size in a shared spill area (k_spill_alloc), filled by a
+// second pass over the triangles (k_bin_spill) that does nothing when no
+// quadrant overflowed.  A quadrant whose list does not fit the spill area,
+// or every quadrant when the global list overflows, walks the BVH instead.
 //
 // Depth skip.  A quadrant's list holds the triangles facing the camera
 // first, then the others, each with a lower bound on the distance t at which
@@ -42,6 +50,7 @@ namespace inrf {
 namespace dev {
 
 constexpr int kQuad = 8;            // bin side in pixels (one wave's quadrant of a tile)
+constexpr int kBinCap = 256;        // slots of a quadrant's list
 constexpr int kBinGlobal = 256;     // capacity of the global list
 constexpr float kBinPad = 1.0f;     // bounding box widening, pixels
 constexpr float kBinFront = 0.05f;  // lambda / |q| of a vertex safely in front (or behind)
@@ -51,32 +60,25 @@ struct BinsC {
     float o[3];                // camera centre
     float sjx, sjb, siy, sib;  // pixel column j = X / lambda * sjx + sjb, row i = Y / lambda * siy + sib
     int32_t W, H, QX, QY;      // image and quadrant grid sizes
-    int32_t* cnt;              // [QX * QY] entries per quadrant (the fill pass counts the others back down)
-    int32_t* fcnt;             // [QX * QY] facing entries per quadrant (counted up by the fill pass)
-    int32_t* off;              // [QX * QY] exclusive offsets within scan runs
-    int32_t* runs;             // scan run carries
-    int32_t* total;            // total entries, then the global list: total[1] = its count, total[2 ..] records
-    int2* entries;             // [E] (triangle record, bits of its distance bound), quadrant after quadrant
-    int64_t E;
-    int32_t clamp;             // the scan adds min(count, clamp) per quadrant, so sums fit 31 bits
+    int32_t* cnt;              // [QX * QY] entries of triangles not facing the camera, per quadrant
+    int32_t* fcnt;             // [QX * QY] entries of facing triangles, per quadrant
+    int32_t* total;            // the global list: total[1] = its count, total[2 ..] records
+    int2* entries;             // [QX * QY][kBinCap] (triangle record, bits of its distance bound)
+    int32_t* base;             // [QX * QY] start of an overflowing quadrant's spill list, -1: none
+    int32_t* sfcnt;            // [QX * QY] spill fill counters: facing entries
+    int32_t* scnt;             // [QX * QY] spill fill counters: the others
+    unsigned long long* top;   // spill entries handed out
+    int2* spill;               // [spill_cap] spill lists
+    int32_t spill_cap;
     float tscale;              // (1 - 1e-4) / |a_f|: distance bound per unit of lambda
 };
-
-// Quadrant q's list [s, e) and whether it holds every record of the quadrant:
-// its count was not clamped by the scan and the list lies inside [0, E).
-__device__ __forceinline__ bool bin_list(const BinsC& b, int q, int64_t& s, int64_t& e) {
-    const int nq = b.QX * b.QY;
-    s = int64_t(b.off[q]) + b.runs[q / kScanRun];
-    e = q + 1 < nq ? int64_t(b.off[q + 1]) + b.runs[(q + 1) / kScanRun] : int64_t(b.total[0]);
-    return e - s < b.clamp && e <= b.E;
-}
 
 // Quadrant range of triangle record k: 0 = no pixel can hit it, 1 = the
 // range [qx0, qx1] x [qy0, qy1], 2 = the global list.
 __device__ __forceinline__ int bin_range(const BinsC& b, const BvhTri* __restrict__ tris, int64_t k, int& qx0,
                                          int& qx1, int& qy0, int& qy1, bool* facing = nullptr,
                                          float* lam_min = nullptr) {
-#pragma clang fp contract(off)  // the count and fill passes must classify every triangle identically
+#pragma clang fp contract(off)  // k_bin and k_bin_spill must classify every triangle identically
     const float4* p = reinterpret_cast<const float4*>(tris + k);
     const float4 v[3] = {p[0], p[1], p[2]};
     float jlo = INFINITY, jhi = -INFINITY, ilo = INFINITY, ihi = -INFINITY, lmin = INFINITY;
@@ -123,49 +125,81 @@ __device__ __forceinline__ int bin_range(const BinsC& b, const BvhTri* __restric
     return 1;
 }
 
-// Clears the quadrant counts and the global list (one thread per quadrant).
+// Clears the quadrant counts, the global list and the spill area's
+// counters (one thread per quadrant).
 __global__ void k_bin_clear(BinsC b) {
     const int q = int(blockIdx.x) * blockDim.x + threadIdx.x;
     if (q < b.QX * b.QY) {
         b.cnt[q] = 0;
         b.fcnt[q] = 0;
+        b.scnt[q] = 0;
+        b.sfcnt[q] = 0;
     }
-    if (q == 0) b.total[1] = 0;
+    if (q == 0) {
+        b.total[1] = 0;
+        *b.top = 0;
+    }
 }
 
-// Count pass (FILL = false) and fill pass (FILL = true), one thread per
-// triangle record.  The fill pass stores a quadrant's facing triangles from
-// the start of its list up (counting fcnt up) and the others from the end
-// down (counting cnt down), only in quadrants whose whole list was kept
-// (bin_list).
-template <bool FILL>
+// One thread per triangle record: the triangle's entry goes into every
+// quadrant its range covers, facing triangles from the start of the list up,
+// the others from the end down; slots past kBinCap are counted but not
+// written.
 __global__ __launch_bounds__(256) void k_bin(BinsC b, const BvhTri* __restrict__ tris, int64_t n_tris) {
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= n_tris) return;
     int qx0, qx1, qy0, qy1;
     bool facing = true;
     float lmin = 0.f;
-    const int r = bin_range(b, tris, k, qx0, qx1, qy0, qy1, FILL ? &facing : nullptr, FILL ? &lmin : nullptr);
+    const int r = bin_range(b, tris, k, qx0, qx1, qy0, qy1, &facing, &lmin);
     const int2 rec = make_int2(int32_t(k), __float_as_int(lmin * b.tscale));
     if (r == 0) return;
     if (r == 2) {
-        if (!FILL) {
-            const int g = atomicAdd(b.total + 1, 1);
-            if (g < kBinGlobal) b.total[2 + g] = int32_t(k);
-        }
+        const int g = atomicAdd(b.total + 1, 1);
+        if (g < kBinGlobal) b.total[2 + g] = int32_t(k);
         return;
     }
     for (int qy = qy0; qy <= qy1; ++qy)
         for (int qx = qx0; qx <= qx1; ++qx) {
-            const int q = qy * b.QX + qx;
-            if (!FILL) {
-                atomicAdd(b.cnt + q, 1);
-            } else {
-                int64_t s, e;
-                const bool whole = bin_list(b, q, s, e);
-                const int slot = facing ? atomicAdd(b.fcnt + q, 1) : atomicSub(b.cnt + q, 1) - 1;
-                if (whole && slot >= 0 && s + slot < e) b.entries[s + slot] = rec;
-            }
+            const int64_t q = int64_t(qy) * b.QX + qx;
+            const int slot = atomicAdd((facing ? b.fcnt : b.cnt) + q, 1);
+            if (slot < kBinCap) b.entries[q * kBinCap + (facing ? slot : kBinCap - 1 - slot)] = rec;
+        }
+}
+
+// One thread per quadrant: a quadrant whose list overflowed gets a spill
+// list of its exact size, or -1 when the spill area has no room for it.
+__global__ void k_spill_alloc(BinsC b) {
+    const int q = int(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q >= b.QX * b.QY) return;
+    const int64_t n = int64_t(b.fcnt[q]) + b.cnt[q];
+    int32_t at = -1;
+    if (n > kBinCap) {
+        const unsigned long long s = atomicAdd(b.top, (unsigned long long)n);
+        if (s + (unsigned long long)n <= (unsigned long long)b.spill_cap) at = int32_t(s);
+    }
+    b.base[q] = at;
+}
+
+// The fill pass again for the quadrants that have a spill list: facing
+// entries from the start of the list up, the others from its end down.
+// Returns at once when no quadrant overflowed.
+__global__ __launch_bounds__(256) void k_bin_spill(BinsC b, const BvhTri* __restrict__ tris, int64_t n_tris) {
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n_tris || *b.top == 0) return;
+    int qx0, qx1, qy0, qy1;
+    bool facing = true;
+    float lmin = 0.f;
+    if (bin_range(b, tris, k, qx0, qx1, qy0, qy1, &facing, &lmin) != 1) return;
+    const int2 rec = make_int2(int32_t(k), __float_as_int(lmin * b.tscale));
+    for (int qy = qy0; qy <= qy1; ++qy)
+        for (int qx = qx0; qx <= qx1; ++qx) {
+            const int64_t q = int64_t(qy) * b.QX + qx;
+            const int32_t at = b.base[q];
+            if (at < 0) continue;
+            const int nf = b.fcnt[q], nb = b.cnt[q];
+            const int slot = atomicAdd((facing ? b.sfcnt : b.scnt) + q, 1);
+            if (slot < (facing ? nf : nb)) b.spill[int64_t(at) + (facing ? slot : nf + nb - 1 - slot)] = rec;
         }
 }
 
@@ -228,13 +262,14 @@ __device__ __forceinline__ void bin_walk(const RayPre& R, const Ax& ax, const in
     }
 }
 
-// The facing part of a quadrant's list, then the rest with the depth skip.
+// The facing part [s, f) of a quadrant's list, then the rest [s2, e) with
+// the depth skip (entry indices relative to ent).
 template <class Ax>
 __device__ __forceinline__ void bin_walk_list(const RayPre& R, const Ax& ax, const int2* __restrict__ ent,
-                                              const float4* __restrict__ tv, int s, int f, int e, bool active,
+                                              const float4* __restrict__ tv, int s, int f, int s2, int e, bool active,
                                               float& best_t, int32_t& best_i) {
     bin_walk<false>(R, ax, ent, tv, s, f, INFINITY, active, best_t, best_i);
-    if (f < e) bin_walk<true>(R, ax, ent, tv, f, e, wave_max_best(active, best_t), active, best_t, best_i);
+    if (s2 < e) bin_walk<true>(R, ax, ent, tv, s2, e, wave_max_best(active, best_t), active, best_t, best_i);
 }
 
 // Closest hit of a wave of camera rays in quadrant (qx, qy) through its
@@ -249,19 +284,20 @@ __device__ void closest_hit_binned(const B& m, const BinsC& b, int qx, int qy, c
                                    float& best_t, int32_t& best_i) {
     if (m.n_tris == 0 || __ballot(active) == 0) return;
     const int q = __builtin_amdgcn_readfirstlane(qy * b.QX + qx);
-    int64_t s64, e64;
-    const bool whole = bin_list(b, q, s64, e64);
+    const int nf = __builtin_amdgcn_readfirstlane(b.fcnt[q]), nb = __builtin_amdgcn_readfirstlane(b.cnt[q]);
     const int g = __builtin_amdgcn_readfirstlane(b.total[1]);
-    if (!__builtin_amdgcn_readfirstlane(int(whole)) || g > kBinGlobal) {
+    const bool fits = int64_t(nf) + nb <= kBinCap;
+    const int at = fits ? 0 : __builtin_amdgcn_readfirstlane(b.base[q]);
+    if (at < 0 || g > kBinGlobal) {  // a spill list that did not fit, or a full global list
         closest_hit_packet(m, R, active, wst, best_t, best_i);
         return;
     }
     // the global list first: its triangles have no distance bound
     for (int k = 0; k < g; ++k) bin_test(R, m.tris, __builtin_amdgcn_readfirstlane(b.total[2 + k]), active, best_t, best_i);
-    // lists lie in [0, E) with E < 2^31 records, so 32-bit bounds suffice
-    const int s = __builtin_amdgcn_readfirstlane(int(s64)), e = __builtin_amdgcn_readfirstlane(int(e64));
-    const int f = min(e, s + __builtin_amdgcn_readfirstlane(b.fcnt[q]));
-    const int2* __restrict__ ent = b.entries;
+    // facing entries [0, nf) of the quadrant's slots and the others
+    // [kBinCap - nb, kBinCap), or the spill list [0, nf) and [nf, nf + nb)
+    const int s = 0, f = nf, s2 = fits ? kBinCap - nb : nf, e = fits ? kBinCap : nf + nb;
+    const int2* __restrict__ ent = fits ? b.entries + int64_t(q) * kBinCap : b.spill + at;
     const float4* __restrict__ tv = reinterpret_cast<const float4*>(m.tris);
     // permutation id: kz (0..2) and whether kx, ky were swapped
     const int perm = 2 * R.kz + (R.kx == (R.kz + 1) % 3 ? 0 : 1);
@@ -269,15 +305,15 @@ __device__ void closest_hit_binned(const B& m, const BinsC& b, int qx, int qy, c
     const int pu = __builtin_amdgcn_readlane(perm, lead);
     if (__ballot(active && perm != pu) == 0) {
         switch (pu) {
-            case 0: bin_walk_list(R, AxisC<1, 2, 0>(), ent, tv, s, f, e, active, best_t, best_i); break;
-            case 1: bin_walk_list(R, AxisC<2, 1, 0>(), ent, tv, s, f, e, active, best_t, best_i); break;
-            case 2: bin_walk_list(R, AxisC<2, 0, 1>(), ent, tv, s, f, e, active, best_t, best_i); break;
-            case 3: bin_walk_list(R, AxisC<0, 2, 1>(), ent, tv, s, f, e, active, best_t, best_i); break;
-            case 4: bin_walk_list(R, AxisC<0, 1, 2>(), ent, tv, s, f, e, active, best_t, best_i); break;
-            default: bin_walk_list(R, AxisC<1, 0, 2>(), ent, tv, s, f, e, active, best_t, best_i); break;
+            case 0: bin_walk_list(R, AxisC<1, 2, 0>(), ent, tv, s, f, s2, e, active, best_t, best_i); break;
+            case 1: bin_walk_list(R, AxisC<2, 1, 0>(), ent, tv, s, f, s2, e, active, best_t, best_i); break;
+            case 2: bin_walk_list(R, AxisC<2, 0, 1>(), ent, tv, s, f, s2, e, active, best_t, best_i); break;
+            case 3: bin_walk_list(R, AxisC<0, 2, 1>(), ent, tv, s, f, s2, e, active, best_t, best_i); break;
+            case 4: bin_walk_list(R, AxisC<0, 1, 2>(), ent, tv, s, f, s2, e, active, best_t, best_i); break;
+            default: bin_walk_list(R, AxisC<1, 0, 2>(), ent, tv, s, f, s2, e, active, best_t, best_i); break;
         }
     } else {
-        bin_walk_list(R, AxisR{R.kx, R.ky, R.kz}, ent, tv, s, f, e, active, best_t, best_i);
+        bin_walk_list(R, AxisR{R.kx, R.ky, R.kz}, ent, tv, s, f, s2, e, active, best_t, best_i);
     }
 }
 

@@ -1,10 +1,10 @@
 // Device entry points of libinrf: closest-hit trace, position encoding, the
 // network alone, and the fused per-ray path (inrf_render / inrf_forward).
 //
-// A camera frame is ten launches on the caller's stream:
-//   k_bin_clear, k_bin (count), k_scan_local, k_scan_runs, k_bin (fill)
-//             sort the proxy's triangles into lists per 8x8-pixel quadrant
-//             of the frame (bin_device.hpp);
+// A camera frame is nine launches on the caller's stream:
+//   k_bin_clear, k_bin, k_spill_alloc, k_bin_spill  sort the proxy's
+//             triangles into lists per 8x8-pixel quadrant of the frame
+//             (bin_device.hpp);
 //   k_trace   one ray per lane, tiles in strip order: generate (camera) or
 //             load (batch) the ray, closest hit with a watertight triangle
 //             test against the wave's quadrant list (camera; the BVH where a
@@ -1028,35 +1028,50 @@ constexpr int kMaxChunks = 2;  // hit counters at the start of the header: the f
 constexpr int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
 
 // Workspace of a trace of up to n rays: counter | records | per-tile
-// records | per-tile (count, base) | per-tile offsets | per-run offsets.  A
+// records | per-tile (count, base) | per-tile offsets | per-run offsets |
+// screen bins (quadrant counters, the global list, the spill area).  A
 // camera of W x H = n pixels has at most ceil(W/16) ceil(H/16) <= n/8 + 2
 // tiles.
+//
+// The quadrant lists of a camera frame share the records' space: the trace
+// reads them before k_compact writes the first record.  The spill area holds
+// n entries (at most INT32_MAX).
 struct WsLayout {
     int64_t recs, tmp, blk, offsets, runs;
-    int64_t qcnt, qfcnt, qoff, qruns, qtotal, entries;  // screen bins of a camera frame (bin_device.hpp)
-    int64_t n_quads, n_entries, end;
-    // extra: 2 more tiles per additional camera of a batch.  A W x H = n
-    // pixel frame has ceil(W/8) ceil(H/8) <= n/8 + 1 quadrants; the bins
-    // hold up to n triangle records (a quadrant whose list does not fit
-    // walks the BVH instead).
+    int64_t qcnt, qfcnt, qtotal, entries;  // screen bins of a camera frame (bin_device.hpp)
+    int64_t qbase, qscnt, qsfcnt, qtop, spill;
+    int64_t n_quads, n_spill, end;
+    // Quadrants of a W x H = n pixel frame: at most (W + 7)(H + 7) / 64,
+    // below n/64 + isqrt(n) + 16 for every aspect ratio up to about 1:70; a
+    // frame with more walks the BVH.
+    static constexpr int64_t isqrt(int64_t n) {  // floor(sqrt(n)), bit by bit
+        int64_t r = 0;
+        for (int64_t b = int64_t(1) << 31; b > 0; b >>= 1)
+            if (r + b <= n / (r + b)) r += b;
+        return r;
+    }
+    // extra: 2 more tiles per additional camera of a batch.
     constexpr explicit WsLayout(int64_t n, int64_t extra = 0)
-        : recs(0), tmp(0), blk(0), offsets(0), runs(0), qcnt(0), qfcnt(0), qoff(0), qruns(0), qtotal(0), entries(0),
-          n_quads(0), n_entries(0), end(0) {
+        : recs(0), tmp(0), blk(0), offsets(0), runs(0), qcnt(0), qfcnt(0), qtotal(0), entries(0), qbase(0), qscnt(0),
+          qsfcnt(0), qtop(0), spill(0), n_quads(0), n_spill(0), end(0) {
         const int64_t nb = n / 8 + 2 + extra, nr = nb / kScanRun + 1 + kMaxChunks;
+        n_quads = n / 64 + isqrt(n) + 16;
         recs = kWsHeader;
-        tmp = align256(recs + n * int64_t(sizeof(HitRec)));
+        entries = recs;
+        tmp = align256(recs + std::max(n * int64_t(sizeof(HitRec)), n_quads * kBinCap * int64_t(sizeof(int2))));
         blk = align256(tmp + n * int64_t(sizeof(HitRec)));
         offsets = align256(blk + nb * int64_t(sizeof(int2)));
         runs = align256(offsets + nb * int64_t(sizeof(int32_t)));
-        n_quads = n / 8 + 1;
-        n_entries = n;
         qcnt = align256(runs + nr * int64_t(sizeof(int32_t)));
         qfcnt = align256(qcnt + n_quads * int64_t(sizeof(int32_t)));
-        qoff = align256(qfcnt + n_quads * int64_t(sizeof(int32_t)));
-        qruns = align256(qoff + n_quads * int64_t(sizeof(int32_t)));
-        qtotal = align256(qruns + (n_quads / kScanRun + 2) * int64_t(sizeof(int32_t)));
-        entries = align256(qtotal + (2 + kBinGlobal) * int64_t(sizeof(int32_t)));
-        end = align256(entries + n_entries * int64_t(sizeof(int2)));
+        qtotal = align256(qfcnt + n_quads * int64_t(sizeof(int32_t)));
+        qbase = align256(qtotal + (2 + kBinGlobal) * int64_t(sizeof(int32_t)));
+        qscnt = align256(qbase + n_quads * int64_t(sizeof(int32_t)));
+        qsfcnt = align256(qscnt + n_quads * int64_t(sizeof(int32_t)));
+        qtop = align256(qsfcnt + n_quads * int64_t(sizeof(int32_t)));
+        spill = align256(qtop + int64_t(sizeof(unsigned long long)));
+        n_spill = std::min<int64_t>(n, INT32_MAX);
+        end = align256(spill + n_spill * int64_t(sizeof(int2)));
     }
 };
 
@@ -1330,35 +1345,34 @@ bool make_bins(const CamC& cam, void* ws, const WsLayout& L, BinsC& b) {
     if (int64_t(b.QX) * b.QY > L.n_quads) return false;
     b.cnt = ws_at<int32_t>(ws, L.qcnt);
     b.fcnt = ws_at<int32_t>(ws, L.qfcnt);
-    b.off = ws_at<int32_t>(ws, L.qoff);
-    b.runs = ws_at<int32_t>(ws, L.qruns);
     b.total = ws_at<int32_t>(ws, L.qtotal);
     b.entries = ws_at<int2>(ws, L.entries);
-    b.E = L.n_entries;
+    b.base = ws_at<int32_t>(ws, L.qbase);
+    b.scnt = ws_at<int32_t>(ws, L.qscnt);
+    b.sfcnt = ws_at<int32_t>(ws, L.qsfcnt);
+    b.top = ws_at<unsigned long long>(ws, L.qtop);
+    b.spill = ws_at<int2>(ws, L.spill);
+    b.spill_cap = int32_t(L.n_spill);
     // distance bound per unit of lambda: t >= lambda / |a_f| for unit rays
     const double af = std::sqrt(double(b.a[6]) * b.a[6] + double(b.a[7]) * b.a[7] + double(b.a[8]) * b.a[8]);
     b.tscale = float((1.0 - 1e-4) / af);
-    b.clamp = int32_t(std::min<int64_t>(L.n_entries + 1, ((int64_t(1) << 31) - 1) / (int64_t(b.QX) * b.QY)));
     return true;
 }
 
-// Sorts the proxy's triangles into the frame's quadrant lists: clear, count,
-// scan, fill.
+// Sorts the proxy's triangles into the frame's quadrant lists: clear, fill,
+// spill lists for the quadrants that overflowed, their fill.
 void bin_frame(const ModelC& c, const BinsC& b, hipStream_t s) {
     const int nq = b.QX * b.QY;
-    hipLaunchKernelGGL(k_bin_clear, dim3(unsigned((nq + 255) / 256)), dim3(256), 0, s, b);
+    const unsigned qgrid = unsigned((nq + 255) / 256), tgrid = unsigned((c.n_tris + 255) / 256);
+    hipLaunchKernelGGL(k_bin_clear, dim3(qgrid), dim3(256), 0, s, b);
     launch_check("k_bin_clear");
     if (c.n_tris == 0) return;
-    const unsigned grid = unsigned((c.n_tris + 255) / 256);
-    hipLaunchKernelGGL(k_bin<false>, dim3(grid), dim3(256), 0, s, b, c.tris, c.n_tris);
+    hipLaunchKernelGGL(k_bin, dim3(tgrid), dim3(256), 0, s, b, c.tris, c.n_tris);
     launch_check("k_bin");
-    const int n_runs = (nq + kScanRun - 1) / kScanRun;
-    hipLaunchKernelGGL(k_scan_local, dim3(n_runs), dim3(kScanThreads), 0, s, b.cnt, 1, nq, b.off, b.runs, b.clamp);
-    launch_check("k_scan_local");
-    hipLaunchKernelGGL(k_scan_runs, dim3(1), dim3(kScanThreads), 0, s, b.runs, n_runs, b.total, nullptr, 0);
-    launch_check("k_scan_runs");
-    hipLaunchKernelGGL(k_bin<true>, dim3(grid), dim3(256), 0, s, b, c.tris, c.n_tris);
-    launch_check("k_bin");
+    hipLaunchKernelGGL(k_spill_alloc, dim3(qgrid), dim3(256), 0, s, b);
+    launch_check("k_spill_alloc");
+    hipLaunchKernelGGL(k_bin_spill, dim3(tgrid), dim3(256), 0, s, b, c.tris, c.n_tris);
+    launch_check("k_bin_spill");
 }
 
 // Clears the hit counter, then traces n rays (camera rays when cam is set),

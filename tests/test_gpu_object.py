@@ -171,6 +171,67 @@ def test_object_render_equals_forward(obj):
     assert torch.equal(a, b)
 
 
+BIN_CAP = 256   # triangles a quadrant's list holds
+
+
+def _quadrant_counts(w, cam):
+    """FP64 count of the triangles whose one-pixel-padded screen box touches
+    each 8x8 quadrant (all three vertices in front of the camera)."""
+    v = w.verts.astype(np.float64)[w.tris]                    # (T, 3, 3)
+    q = v - cam.origin.astype(np.float64)
+    x, y, lam = (q @ cam.right.astype(np.float64), q @ cam.up.astype(np.float64),
+                 q @ cam.forward.astype(np.float64))
+    ty = float(cam.tan_half_fov_y)
+    tx = ty * cam.width / cam.height
+    j = x / lam * (cam.width / (2 * tx)) + 0.5 * cam.width - 0.5
+    i = -y / lam * (cam.height / (2 * ty)) + 0.5 * cam.height - 0.5
+    jlo, jhi = np.floor(j.min(1) - 1), np.ceil(j.max(1) + 1)
+    ilo, ihi = np.floor(i.min(1) - 1), np.ceil(i.max(1) + 1)
+    ok = (lam.min(1) > 0) & (jhi >= 0) & (ihi >= 0) & (jlo <= cam.width - 1) & (ilo <= cam.height - 1)
+    qx0 = (np.maximum(jlo, 0) // 8).astype(int)[ok]
+    qx1 = (np.minimum(jhi, cam.width - 1) // 8).astype(int)[ok]
+    qy0 = (np.maximum(ilo, 0) // 8).astype(int)[ok]
+    qy1 = (np.minimum(ihi, cam.height - 1) // 8).astype(int)[ok]
+    cnt = np.zeros(((cam.height + 7) // 8, (cam.width + 7) // 8), np.int64)
+    for b in range(int((qy1 - qy0).max(initial=0)) + 1):
+        for a in range(int((qx1 - qx0).max(initial=0)) + 1):
+            m = (qy0 + b <= qy1) & (qx0 + a <= qx1)
+            np.add.at(cnt, (qy0[m] + b, qx0[m] + a), 1)
+    return cnt
+
+
+@pytest.mark.parametrize("wh", [(1920, 1080), (96, 64), (1, 2000), (4000, 3)])
+def test_object_overflowing_bins_equal_forward(obj, wh):
+    """Quadrants with more triangles than their 256 slots get spill lists of
+    their exact size (1080p: a few such quadrants, checked on the CPU); where
+    the spill area, one entry per pixel, has no room for them (96x64: most
+    covered quadrants hold thousands of triangles) and in frames with more
+    quadrants than the workspace lays out (thin strips) the quadrants are
+    traced through the BVH.  Every pixel equals the ray-batch path, bit for
+    bit."""
+    import paper_2303_04086_amd as P
+    w, R = obj
+    cam = synth.fibonacci_cameras(8, 2.0, *wh)[6]
+    if wh == (1920, 1080):
+        cnt = _quadrant_counts(w, cam)
+        assert (cnt > BIN_CAP + 32).any() and ((cnt > 0) & (cnt < BIN_CAP - 32)).sum() > 0.9 * (cnt > 0).sum()
+    if wh == (96, 64):
+        cnt = _quadrant_counts(w, cam)
+        assert (cnt[cnt > 0] > BIN_CAP + 32).mean() > 0.5
+    n = cam.width * cam.height
+    t1 = torch.empty(n, dtype=torch.int32, device="cuda")
+    t2 = torch.empty(n, dtype=torch.int32, device="cuda")
+    d1 = torch.empty(n, device="cuda")
+    d2 = torch.empty(n, device="cuda")
+    a = R.render(cam, "fp16", "f16", tri=t1, depth=d1).reshape(-1, 4)
+    o, d = P.camera_rays(cam)
+    b = R.forward(o, d, "fp16", "f16", tri=t2, depth=d2)
+    assert (t1 >= 0).any()
+    assert torch.equal(t1, t2)
+    assert torch.equal(d1, d2)
+    assert torch.equal(a, b)
+
+
 # FP32 hit points x = o + t d (camera-distance origins, |o| <= 2.5) carry
 # up to ~4e-7 absolute error against the oracle's FP64 ones (rounding of
 # t d and of the sum, and t's own rounding); a corner weight of level N is a
