@@ -52,6 +52,14 @@ struct alignas(16) HitRec {
     int32_t pad;
 };
 
+// The hit record of a single camera's frame: the shading kernel derives the
+// direction from the pixel again (camera_dir, unit_of), so the record is
+// half the size of a HitRec.
+struct alignas(16) CamHit {
+    float x, y, z;
+    int32_t out;  // output (pixel) index
+};
+
 struct CamC {
     float o[3], r[3], u[3], f[3];
     float tan_y, tan_x;  // tan(fov_y/2) and tan(fov_y/2)*W/H
@@ -82,12 +90,21 @@ __host__ __device__ __forceinline__ void tile_at(int t, int tiles_x, int tiles_y
 // rays (and inrf_camera_rays) calls this one function, so their rays are
 // bit-identical.
 __device__ __forceinline__ float3 camera_dir(const CamC& cam, int row, int col) {
+#pragma clang fp contract(off)  // the same rounding in every kernel that inlines it
     const float sx = ((2.f * (float(col) + 0.5f)) / float(cam.W) - 1.f) * cam.tan_x;
     const float sy = (1.f - (2.f * (float(row) + 0.5f)) / float(cam.H)) * cam.tan_y;
     const float3 v = make_float3(cam.f[0] + sx * cam.r[0] + sy * cam.u[0], cam.f[1] + sx * cam.r[1] + sy * cam.u[1],
                                  cam.f[2] + sx * cam.r[2] + sy * cam.u[2]);
     const float inv = 1.f / sqrtf(v.x * v.x + v.y * v.y + v.z * v.z);
     return make_float3(v.x * inv, v.y * inv, v.z * inv);
+}
+
+// d / |d|, the direction a hit record holds (the trace and the shading of
+// compact camera records both take it from here).
+__device__ __forceinline__ float3 unit_of(float3 d) {
+#pragma clang fp contract(off)
+    const float inv = 1.f / sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
+    return make_float3(d.x * inv, d.y * inv, d.z * inv);
 }
 
 // Cameras traced by one launch: tiles of camera j are [c[j].tile0, c[j+1].tile0).
@@ -105,7 +122,8 @@ struct TraceArgs {
     float* rgba;    // nullable
     float* depth;   // nullable
     int32_t* tri;   // nullable
-    HitRec* tmp;    // nullable: no records (trace only); else hit records of workgroup b at blk[b].y
+    void* tmp;      // nullable: no records (trace only); else hit records of workgroup b at blk[b].y
+                    // (CamHit for a single camera's frame, else HitRec)
     int2* blk;      // per workgroup: (hit count, first record index in tmp)
 };
 
@@ -450,17 +468,13 @@ __global__ __launch_bounds__(kThreads) void k_trace(ModelC m, CamSet<NCAM> cams,
         }
         if (hit) {
             const int64_t pos = base + before + __popcll(mask & ((uint64_t(1) << lane) - 1));
-            const float inv = 1.f / sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
-            HitRec h;
-            h.x = clamp01(o.x + t * d.x);
-            h.y = clamp01(o.y + t * d.y);
-            h.z = clamp01(o.z + t * d.z);
-            h.out = int32_t(ray);
-            h.dx = d.x * inv;
-            h.dy = d.y * inv;
-            h.dz = d.z * inv;
-            h.pad = 0;
-            a.tmp[pos] = h;
+            const float x = clamp01(o.x + t * d.x), y = clamp01(o.y + t * d.y), z = clamp01(o.z + t * d.z);
+            if constexpr (CAMERA && NCAM == 1) {
+                static_cast<CamHit*>(a.tmp)[pos] = CamHit{x, y, z, int32_t(ray)};
+            } else {
+                const float3 u = unit_of(d);
+                static_cast<HitRec*>(a.tmp)[pos] = HitRec{x, y, z, int32_t(ray), u.x, u.y, u.z, 0};
+            }
         }
         if (threadIdx.x == 0) a.blk[blockIdx.x] = make_int2(total, int(base));
     }
@@ -539,9 +553,11 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_runs(int32_t* __restrict_
 // workgroup for a single object, every object's run of tile b for a scene
 // (runs stored [object][tile]), so a scene launches one workgroup per tile
 // rather than one per (object, tile).
+template <class Rec>
 __global__ __launch_bounds__(kThreads) void k_compact(const int2* __restrict__ blk, const int32_t* __restrict__ offsets,
-                                                      const int32_t* __restrict__ runs, const HitRec* __restrict__ tmp,
-                                                      HitRec* __restrict__ recs, int n_groups, int stride) {
+                                                      const int32_t* __restrict__ runs, const Rec* __restrict__ tmp,
+                                                      Rec* __restrict__ recs, int n_groups, int stride) {
+    constexpr int kWords = int(sizeof(Rec) / sizeof(float4));
     // the runs' (count, source) and destinations, all requested at once (n_groups <= kThreads)
     __shared__ int3 s_run[kThreads];
     if (int(threadIdx.x) < n_groups) {
@@ -555,8 +571,8 @@ __global__ __launch_bounds__(kThreads) void k_compact(const int2* __restrict__ b
         for (int i = threadIdx.x; i < r.x; i += kThreads) {
             const float4* src = reinterpret_cast<const float4*>(tmp + r.y + i);
             float4* dst = reinterpret_cast<float4*>(recs + r.z + i);
-            dst[0] = src[0];
-            dst[1] = src[1];
+#pragma unroll
+            for (int w = 0; w < kWords; ++w) dst[w] = src[w];
         }
     }
 }
@@ -630,11 +646,12 @@ struct ShadeShape {
 // NOLF (the paper's own i-NOLF form): the record's pad holds the ray's
 // coarse opacity, a further network input, and the colour buffer holds the
 // diffuse colour and tint of the hit, which the outputs complete as
-// (c_d + t c_s, alpha).
+// (c_d + t c_s, alpha).  With cam->W > 0 the records are the CamHit records
+// of that camera's frame.
 template <class TableT, class P, int LPG, bool NOLF, class M>
 __device__ __forceinline__ void shade_step(const M& m, const typename Mfma<P>::vec* W,
-                                           typename TileElem<P>::type* tile, const HitRec* __restrict__ recs,
-                                           int64_t base, int64_t n, float* __restrict__ rgba) {
+                                           typename TileElem<P>::type* tile, const void* __restrict__ recs,
+                                           const CamC& cam, int64_t base, int64_t n, float* __restrict__ rgba) {
     constexpr int X = NOLF ? 1 : 0;
     typedef Mfma<P> Mf;
     typedef typename Mf::vec Vec;
@@ -644,8 +661,17 @@ __device__ __forceinline__ void shade_step(const M& m, const typename Mfma<P>::v
     const int64_t i = base + lane;
     const bool act = i < n;
     HitRec h;
-    if (act) h = recs[i];
-    else h = HitRec{0.f, 0.f, 0.f, 0, 0.f, 0.f, 1.f, 0};
+    if (cam.W > 0) {  // wave-uniform
+        const CamHit c = act ? static_cast<const CamHit*>(recs)[i] : CamHit{0.f, 0.f, 0.f, int32_t(cam.pix0)};
+        const int p = c.out - int(cam.pix0);  // a single camera: pix0 = 0, pixels < 2^31
+        const int row = p / cam.W, col = p - row * cam.W;
+        const float3 u = unit_of(camera_dir(cam, row, col));
+        h = HitRec{c.x, c.y, c.z, c.out, u.x, u.y, u.z, 0};
+    } else if (act) {
+        h = static_cast<const HitRec*>(recs)[i];
+    } else {
+        h = HitRec{0.f, 0.f, 0.f, 0, 0.f, 0.f, 1.f, 0};
+    }
     float e[S::F];
 #pragma unroll
     for (int k = 2 * S::LMAX; k < S::F; ++k) e[k] = 0.f;
@@ -687,13 +713,12 @@ __device__ __forceinline__ void shade_step(const M& m, const typename Mfma<P>::v
 }
 
 // Persistent waves over the packed hit list [first, counter), 64 hits per
-// wave step (shade_step).
+// wave step (shade_step); CamHit records of camera `cam` when cam.W > 0,
+// else HitRec records.
 template <class TableT, class P, int LPG, bool NOLF = false>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(LPG <= 4 ? 2 : 1)))
-void k_shade(ModelC m, const HitRec* __restrict__ recs,
-                                                                   const int32_t* __restrict__ first,
-                                                                   const int32_t* __restrict__ counter,
-                                                                   float* __restrict__ rgba) {
+void k_shade(ModelC m, const void* __restrict__ recs, CamC cam, const int32_t* __restrict__ first,
+             const int32_t* __restrict__ counter, float* __restrict__ rgba) {
     constexpr int X = NOLF ? 1 : 0;
     typedef typename Mfma<P>::vec Vec;
     typedef ShadeShape<P, LPG, X> S;
@@ -710,7 +735,7 @@ void k_shade(ModelC m, const HitRec* __restrict__ recs,
     __syncthreads();
     for (int64_t base = lo + (int64_t(blockIdx.x) * (kThreads / 64) + threadIdx.x / 64) * 64; base < n;
          base += int64_t(gridDim.x) * kThreads)
-        shade_step<TableT, P, LPG, NOLF>(m, W, tile, recs, base, n, rgba);
+        shade_step<TableT, P, LPG, NOLF>(m, W, tile, recs, cam, base, n, rgba);
 }
 
 // The shading view of one object of a scene: its tables, weights and level
@@ -769,7 +794,7 @@ __global__ __launch_bounds__(kThreads) INRF_MFMA_VGPR void k_shade_scene(ShadeSe
         }
         const int64_t base = seg[obj] + int64_t(c - first_chunk) * kThreads + (threadIdx.x / 64) * 64;
         const int64_t n = seg[obj + 1];
-        if (base < n) shade_step<TableT, P, LPG, false>(ss.m[obj], W, tile, recs, base, n, rgba);
+        if (base < n) shade_step<TableT, P, LPG, false>(ss.m[obj], W, tile, recs, CamC{}, base, n, rgba);
     }
 }
 
@@ -1204,11 +1229,12 @@ unsigned resident_grid(K kernel, size_t lds) {
 }
 
 template <class TableT, class P, int LPG>
-void launch_shade_t(const ModelC& c, const HitRec* recs, const int32_t* first, const int32_t* counter, float* rgba,
-                    hipStream_t s) {
+void launch_shade_t(const ModelC& c, const void* recs, const CamC& cam, const int32_t* first, const int32_t* counter,
+                    float* rgba, hipStream_t s) {
     const size_t lds = ShadeShape<P, LPG>::lds_bytes;
     auto kern = k_shade<TableT, P, LPG>;
-    hipLaunchKernelGGL(kern, dim3(resident_grid(kern, lds)), dim3(kThreads), lds, s, c, recs, first, counter, rgba);
+    hipLaunchKernelGGL(kern, dim3(resident_grid(kern, lds)), dim3(kThreads), lds, s, c, recs, cam, first, counter,
+                       rgba);
 }
 
 template <class P, int LPG>
@@ -1260,15 +1286,18 @@ void launch_mlp_enc_t(const ModelC& c, const void* enc, const float* dir, int64_
         default: fail(INRF_E_UNSUPPORTED, "level count");     \
     }
 
+// HitRec records, or the CamHit records of camera *cam's frame.
 template <class TableT>
-void launch_shade(const ModelC& c, int32_t precision, const HitRec* recs, const int32_t* first,
-                  const int32_t* counter, float* rgba, hipStream_t s) {
-#define INRF_SHADE(LPG)                                                                                 \
-    do {                                                                                               \
-        if (precision == INRF_PREC_FP32) launch_shade_t<TableT, float, LPG>(c, recs, first, counter, rgba, s); \
-        else if (precision == INRF_PREC_FP16)                                                          \
-            launch_shade_t<TableT, _Float16, LPG>(c, recs, first, counter, rgba, s);                   \
-        else launch_shade_t<TableT, __bf16, LPG>(c, recs, first, counter, rgba, s);                    \
+void launch_shade(const ModelC& c, int32_t precision, const void* recs, const int32_t* first,
+                  const int32_t* counter, float* rgba, hipStream_t s, const CamC* cam = nullptr) {
+    CamC none{};
+    const CamC& k = cam ? *cam : none;
+#define INRF_SHADE(LPG)                                                                                      \
+    do {                                                                                                    \
+        if (precision == INRF_PREC_FP32) launch_shade_t<TableT, float, LPG>(c, recs, k, first, counter, rgba, s); \
+        else if (precision == INRF_PREC_FP16)                                                               \
+            launch_shade_t<TableT, _Float16, LPG>(c, recs, k, first, counter, rgba, s);                     \
+        else launch_shade_t<TableT, __bf16, LPG>(c, recs, k, first, counter, rgba, s);                      \
     } while (0)
     INRF_LPG_SWITCH(c.n_levels, INRF_SHADE)
 #undef INRF_SHADE
@@ -1427,7 +1456,12 @@ void trace_to_hits(const ModelC& c, const CamSet<NCAM>* cams, const float* ray_o
     hipLaunchKernelGGL(k_scan_runs, dim3(1), dim3(kScanThreads), 0, s, runs, n_runs, counter, counter + 1,
                        kMaxChunks - 1);
     launch_check("k_scan_runs");
-    hipLaunchKernelGGL(k_compact, dim3(n_blk), dim3(kThreads), 0, s, blk, offsets, runs, a.tmp, recs, 1, n_blk);
+    if (cams && NCAM == 1)
+        hipLaunchKernelGGL(k_compact<CamHit>, dim3(n_blk), dim3(kThreads), 0, s, blk, offsets, runs,
+                           static_cast<const CamHit*>(a.tmp), ws_at<CamHit>(ws, L.recs), 1, n_blk);
+    else
+        hipLaunchKernelGGL(k_compact<HitRec>, dim3(n_blk), dim3(kThreads), 0, s, blk, offsets, runs,
+                           static_cast<const HitRec*>(a.tmp), recs, 1, n_blk);
     launch_check("k_compact");
 }
 
@@ -1460,8 +1494,10 @@ void run_path(const inrf_model* m, int32_t precision, const CamSet<NCAM>* cams, 
     const HitRec* recs = ws_at<HitRec>(ws, L.recs);
     trace_to_hits(c, cams, ray_o, ray_d, n, rgba, depth, tri, ws, s, bins);
     record(events, 1, s);
-    if (c.table_dtype == INRF_F32) launch_shade<float>(c, precision, recs, nullptr, counter, rgba, s);
-    else launch_shade<__half>(c, precision, recs, nullptr, counter, rgba, s);
+    // a single camera's records are CamHit records
+    const CamC* rec_cam = (cams && NCAM == 1) ? &cams->c[0] : nullptr;
+    if (c.table_dtype == INRF_F32) launch_shade<float>(c, precision, recs, nullptr, counter, rgba, s, rec_cam);
+    else launch_shade<__half>(c, precision, recs, nullptr, counter, rgba, s, rec_cam);
     launch_check("k_shade");
     record(events, 2, s);
 }
@@ -1669,7 +1705,8 @@ void run_scene(const inrf_instance* objects, int32_t n_objs, int32_t precision, 
     hipLaunchKernelGGL(k_scan_runs, dim3(1), dim3(kScanThreads), 0, s, runs, n_runs, counter, counter + 1,
                        kMaxChunks - 1);
     launch_check("k_scan_runs");
-    hipLaunchKernelGGL(k_compact, dim3(n_tiles), dim3(kThreads), 0, s, blk, offsets, runs, a.tmp, recs, n_objs, n_tiles);
+    hipLaunchKernelGGL(k_compact<HitRec>, dim3(n_tiles), dim3(kThreads), 0, s, blk, offsets, runs,
+                       static_cast<const HitRec*>(a.tmp), recs, n_objs, n_tiles);
     launch_check("k_compact");
     hipLaunchKernelGGL(k_segments, dim3(1), dim3(64), 0, s, offsets, runs, n_tiles, n_objs, counter, seg);
     launch_check("k_segments");
@@ -1746,7 +1783,8 @@ template <class TableT, class P, int LPG>
 void launch_shade_nolf_t(const ModelC& c, const HitRec* recs, const int32_t* counter, float* rgba, hipStream_t s) {
     const size_t lds = ShadeShape<P, LPG, 1>::lds_bytes;
     auto kern = k_shade<TableT, P, LPG, true>;
-    hipLaunchKernelGGL(kern, dim3(resident_grid(kern, lds)), dim3(kThreads), lds, s, c, recs, nullptr, counter, rgba);
+    hipLaunchKernelGGL(kern, dim3(resident_grid(kern, lds)), dim3(kThreads), lds, s, c, static_cast<const void*>(recs),
+                       CamC{}, nullptr, counter, rgba);
 }
 
 template <class TableT>
@@ -1808,7 +1846,8 @@ void run_nolf(const inrf_model* m, const inrf_cubes* cubes, int32_t precision, c
     hipLaunchKernelGGL(k_scan_runs, dim3(1), dim3(kScanThreads), 0, s, runs, n_runs, counter, counter + 1,
                        kMaxChunks - 1);
     launch_check("k_scan_runs");
-    hipLaunchKernelGGL(k_compact, dim3(n_blk), dim3(kThreads), 0, s, blk, offsets, runs, a.tmp, recs, 1, n_blk);
+    hipLaunchKernelGGL(k_compact<HitRec>, dim3(n_blk), dim3(kThreads), 0, s, blk, offsets, runs,
+                       static_cast<const HitRec*>(a.tmp), recs, 1, n_blk);
     launch_check("k_compact");
     if (c.table_dtype == INRF_F32) launch_shade_nolf<float>(c, precision, recs, counter, rgba, s);
     else launch_shade_nolf<__half>(c, precision, recs, counter, rgba, s);

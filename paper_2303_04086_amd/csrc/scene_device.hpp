@@ -129,13 +129,13 @@ __global__ __launch_bounds__(kThreads) void k_trace_scene(SceneC sc, CamSet<NCAM
             if (best_k != k) continue;
             const ObjC& ob = sc.o[k];
             const float3 oo = xform(ob.m, ob.c, o, true), dd = xform(ob.m, ob.c, d, false);
-            const float il = 1.f / sqrtf(dd.x * dd.x + dd.y * dd.y + dd.z * dd.z);
+            const float3 u = unit_of(dd);
             h.x = clamp01(oo.x + best_t * dd.x);
             h.y = clamp01(oo.y + best_t * dd.y);
             h.z = clamp01(oo.z + best_t * dd.z);
-            h.dx = dd.x * il;
-            h.dy = dd.y * il;
-            h.dz = dd.z * il;
+            h.dx = u.x;
+            h.dy = u.y;
+            h.dz = u.z;
         }
         h.out = int32_t(ray);
         h.pad = best_k;
