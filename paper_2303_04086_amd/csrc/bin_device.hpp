@@ -3,7 +3,8 @@
 // centre, so the triangles a ray can hit are those whose projection covers
 // its pixel.  Each frame therefore sorts the triangles into lists per 8x8
 // pixel quadrant (the pixels one wave traces): a triangle goes into every
-// quadrant its padded screen bounding box touches.  A wave then runs the
+// quadrant its padded screen bounding box touches, less those the edge test
+// below rules out.  A wave then runs the
 // same watertight test on the same FP32 rays against its quadrant's list
 // instead of walking the BVH, and keeps the nearest hit (ties to the lower
 // triangle index) -- the result the BVH gives, since every triangle a ray
@@ -23,6 +24,13 @@
 // triangle whose vertices all have lambda <= -0.05 |q| lies behind the
 // camera and is never hit.  Any other triangle (crossing the camera plane)
 // goes into a global list that every quadrant tests.
+//
+// Edge test.  Within its bounding box, a triangle skips every quadrant whose
+// pixel centres all lie more than kBinPad from the projected triangle: some
+// edge line, moved out by kBinPad, has them all on its outer side (the
+// padded triangle lies inside the three moved half-planes).  A sliver whose
+// projected area is too small for the rounding of its vertices to leave the
+// winding certain keeps its whole box.
 //
 // Lists.  Each quadrant has kBinCap slots, filled in one pass (k_bin):
 // facing triangles from the start up, the others from the end down, each
@@ -54,6 +62,7 @@ constexpr int kBinCap = 256;        // slots of a quadrant's list
 constexpr int kBinGlobal = 256;     // capacity of the global list
 constexpr float kBinPad = 1.0f;     // bounding box widening, pixels
 constexpr float kBinFront = 0.05f;  // lambda / |q| of a vertex safely in front (or behind)
+constexpr float kBinSliver = 0.05f; // |twice the projected area| / perimeter below which the edge test is off
 
 struct BinsC {
     float a[9];                // rows of the inverse camera basis: X (0..2), Y (3..5), lambda (6..8)
@@ -77,7 +86,7 @@ struct BinsC {
 // range [qx0, qx1] x [qy0, qy1], 2 = the global list.
 __device__ __forceinline__ int bin_range(const BinsC& b, const BvhTri* __restrict__ tris, int64_t k, int& qx0,
                                          int& qx1, int& qy0, int& qy1, bool* facing = nullptr,
-                                         float* lam_min = nullptr) {
+                                         float* lam_min = nullptr, float* pj = nullptr, float* pi = nullptr) {
 #pragma clang fp contract(off)  // k_bin and k_bin_spill must classify every triangle identically
     const float4* p = reinterpret_cast<const float4*>(tris + k);
     const float4 v[3] = {p[0], p[1], p[2]};
@@ -98,6 +107,8 @@ __device__ __forceinline__ int bin_range(const BinsC& b, const BvhTri* __restric
         behind += lam <= -lim && lim > 0.f;
         const float il = 1.f / lam;
         const float j = X * il * b.sjx + b.sjb, i = Y * il * b.siy + b.sib;
+        if (pj) pj[c] = j;
+        if (pi) pi[c] = i;
         jlo = fminf(jlo, j);
         jhi = fmaxf(jhi, j);
         ilo = fminf(ilo, i);
@@ -125,6 +136,48 @@ __device__ __forceinline__ int bin_range(const BinsC& b, const BvhTri* __restric
     return 1;
 }
 
+// Edge functions of a projected triangle (column j, row i of its vertices),
+// each moved out by kBinPad and oriented so that e(x, y) = a x + b y + c >= 0
+// holds on the padded triangle's side.
+struct BinEdges {
+    float a[3], b[3], c[3];
+    bool use;  // false: a sliver, test the whole bounding box
+};
+
+__device__ __forceinline__ BinEdges bin_edges(const float* pj, const float* pi) {
+#pragma clang fp contract(off)  // k_bin and k_bin_spill must agree on every quadrant
+    BinEdges E;
+    const float A = (pj[1] - pj[0]) * (pi[2] - pi[0]) - (pj[2] - pj[0]) * (pi[1] - pi[0]);
+    const float s = A > 0.f ? 1.f : -1.f;
+    float per = 0.f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int k1 = k == 2 ? 0 : k + 1;
+        const float ej = pj[k1] - pj[k], ei = pi[k1] - pi[k];
+        const float len = sqrtf(ej * ej + ei * ei);
+        per += len;
+        E.a[k] = -s * ei;
+        E.b[k] = s * ej;
+        E.c[k] = s * (ei * pj[k] - ej * pi[k]) + kBinPad * len;
+    }
+    E.use = fabsf(A) > kBinSliver * per && isfinite(A) && isfinite(per);
+    return E;
+}
+
+// Whether quadrant (qx, qy) has a pixel centre on the inner side of all
+// three moved edges: each edge is tested at the corner of the quadrant's
+// pixel-centre square where it is largest.
+__device__ __forceinline__ bool bin_touches(const BinEdges& E, int qx, int qy) {
+#pragma clang fp contract(off)
+    if (!E.use) return true;
+    const float x0 = float(kQuad * qx), y0 = float(kQuad * qy);
+    const float x1 = x0 + float(kQuad - 1), y1 = y0 + float(kQuad - 1);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        if (E.a[k] * (E.a[k] > 0.f ? x1 : x0) + E.b[k] * (E.b[k] > 0.f ? y1 : y0) + E.c[k] < 0.f) return false;
+    return true;
+}
+
 // Clears the quadrant counts, the global list and the spill area's
 // counters (one thread per quadrant).
 __global__ void k_bin_clear(BinsC b) {
@@ -142,7 +195,7 @@ __global__ void k_bin_clear(BinsC b) {
 }
 
 // One thread per triangle record: the triangle's entry goes into every
-// quadrant its range covers, facing triangles from the start of the list up,
+// quadrant of its range that the edge test keeps, facing triangles from the start of the list up,
 // the others from the end down; slots past kBinCap are counted but not
 // written.
 __global__ __launch_bounds__(256) void k_bin(BinsC b, const BvhTri* __restrict__ tris, int64_t n_tris) {
@@ -150,8 +203,8 @@ __global__ __launch_bounds__(256) void k_bin(BinsC b, const BvhTri* __restrict__
     if (k >= n_tris) return;
     int qx0, qx1, qy0, qy1;
     bool facing = true;
-    float lmin = 0.f;
-    const int r = bin_range(b, tris, k, qx0, qx1, qy0, qy1, &facing, &lmin);
+    float lmin = 0.f, pj[3], pi[3];
+    const int r = bin_range(b, tris, k, qx0, qx1, qy0, qy1, &facing, &lmin, pj, pi);
     const int2 rec = make_int2(int32_t(k), __float_as_int(lmin * b.tscale));
     if (r == 0) return;
     if (r == 2) {
@@ -159,8 +212,10 @@ __global__ __launch_bounds__(256) void k_bin(BinsC b, const BvhTri* __restrict__
         if (g < kBinGlobal) b.total[2 + g] = int32_t(k);
         return;
     }
+    const BinEdges E = bin_edges(pj, pi);
     for (int qy = qy0; qy <= qy1; ++qy)
         for (int qx = qx0; qx <= qx1; ++qx) {
+            if (!bin_touches(E, qx, qy)) continue;
             const int64_t q = int64_t(qy) * b.QX + qx;
             const int slot = atomicAdd((facing ? b.fcnt : b.cnt) + q, 1);
             if (slot < kBinCap) b.entries[q * kBinCap + (facing ? slot : kBinCap - 1 - slot)] = rec;
@@ -189,11 +244,13 @@ __global__ __launch_bounds__(256) void k_bin_spill(BinsC b, const BvhTri* __rest
     if (k >= n_tris || *b.top == 0) return;
     int qx0, qx1, qy0, qy1;
     bool facing = true;
-    float lmin = 0.f;
-    if (bin_range(b, tris, k, qx0, qx1, qy0, qy1, &facing, &lmin) != 1) return;
+    float lmin = 0.f, pj[3], pi[3];
+    if (bin_range(b, tris, k, qx0, qx1, qy0, qy1, &facing, &lmin, pj, pi) != 1) return;
     const int2 rec = make_int2(int32_t(k), __float_as_int(lmin * b.tscale));
+    const BinEdges E = bin_edges(pj, pi);
     for (int qy = qy0; qy <= qy1; ++qy)
         for (int qx = qx0; qx <= qx1; ++qx) {
+            if (!bin_touches(E, qx, qy)) continue;
             const int64_t q = int64_t(qy) * b.QX + qx;
             const int32_t at = b.base[q];
             if (at < 0) continue;

@@ -175,8 +175,10 @@ BIN_CAP = 256   # triangles a quadrant's list holds
 
 
 def _quadrant_counts(w, cam):
-    """FP64 count of the triangles whose one-pixel-padded screen box touches
-    each 8x8 quadrant (all three vertices in front of the camera)."""
+    """FP64 count of the triangles (all three vertices in front of the
+    camera) whose one-pixel-padded screen box touches each 8x8 quadrant and
+    which come within one pixel of a pixel centre of that quadrant: the
+    lists the binned trace builds, up to rounding."""
     v = w.verts.astype(np.float64)[w.tris]                    # (T, 3, 3)
     q = v - cam.origin.astype(np.float64)
     x, y, lam = (q @ cam.right.astype(np.float64), q @ cam.up.astype(np.float64),
@@ -188,14 +190,27 @@ def _quadrant_counts(w, cam):
     jlo, jhi = np.floor(j.min(1) - 1), np.ceil(j.max(1) + 1)
     ilo, ihi = np.floor(i.min(1) - 1), np.ceil(i.max(1) + 1)
     ok = (lam.min(1) > 0) & (jhi >= 0) & (ihi >= 0) & (jlo <= cam.width - 1) & (ilo <= cam.height - 1)
-    qx0 = (np.maximum(jlo, 0) // 8).astype(int)[ok]
-    qx1 = (np.minimum(jhi, cam.width - 1) // 8).astype(int)[ok]
-    qy0 = (np.maximum(ilo, 0) // 8).astype(int)[ok]
-    qy1 = (np.minimum(ihi, cam.height - 1) // 8).astype(int)[ok]
+    # edge lines of the projected triangle moved out by one pixel, inner side >= 0
+    area = (j[:, 1] - j[:, 0]) * (i[:, 2] - i[:, 0]) - (j[:, 2] - j[:, 0]) * (i[:, 1] - i[:, 0])
+    s = np.where(area > 0, 1.0, -1.0)
+    edges, perimeter = [], 0.0
+    for k in range(3):
+        ej, ei = j[:, (k + 1) % 3] - j[:, k], i[:, (k + 1) % 3] - i[:, k]
+        edges.append((-s * ei, s * ej, s * (ei * j[:, k] - ej * i[:, k]) + np.hypot(ej, ei)))
+        perimeter = perimeter + np.hypot(ej, ei)
+    sliver = ~(np.abs(area) > 0.05 * perimeter)    # keeps its whole box
+    qx0 = (np.maximum(jlo, 0) // 8).astype(int)
+    qx1 = (np.minimum(jhi, cam.width - 1) // 8).astype(int)
+    qy0 = (np.maximum(ilo, 0) // 8).astype(int)
+    qy1 = (np.minimum(ihi, cam.height - 1) // 8).astype(int)
     cnt = np.zeros(((cam.height + 7) // 8, (cam.width + 7) // 8), np.int64)
-    for b in range(int((qy1 - qy0).max(initial=0)) + 1):
-        for a in range(int((qx1 - qx0).max(initial=0)) + 1):
-            m = (qy0 + b <= qy1) & (qx0 + a <= qx1)
+    for b in range(int((qy1 - qy0)[ok].max(initial=0)) + 1):
+        for a in range(int((qx1 - qx0)[ok].max(initial=0)) + 1):
+            x0, y0 = 8.0 * (qx0 + a), 8.0 * (qy0 + b)
+            inside = np.ones(len(ok), bool)
+            for ea, eb, ec in edges:
+                inside &= ea * np.where(ea > 0, x0 + 7, x0) + eb * np.where(eb > 0, y0 + 7, y0) + ec >= 0
+            m = ok & (inside | sliver) & (qy0 + b <= qy1) & (qx0 + a <= qx1)
             np.add.at(cnt, (qy0[m] + b, qx0[m] + a), 1)
     return cnt
 
