@@ -410,6 +410,7 @@ __global__ __launch_bounds__(kThreads) void k_trace(ModelC m, CamSet<NCAM> cams,
     bool valid;
     float3 o, d;
     int qx = 0, qy = 0;  // the wave's quadrant (camera)
+    bool empty = false;  // binned: the wave's quadrant has no triangle to test (wave-uniform)
     if (CAMERA) {
         int j = 0;  // the camera of this tile (wave-uniform)
         for (int k = 1; k < NCAM && k < cams.n; ++k)
@@ -424,7 +425,16 @@ __global__ __launch_bounds__(kThreads) void k_trace(ModelC m, CamSet<NCAM> cams,
         valid = row < cam.H && col < cam.W;
         ray = cam.pix0 + int64_t(row) * cam.W + col;
         base = cam.pix0 + int64_t(ty) * kTile * cam.W + int64_t(tx) * kTile * min(kTile, cam.H - ty * kTile);
-        d = camera_dir(cam, row, col);
+        if constexpr (BINNED) {
+            if (qx < bins.QX && qy < bins.QY) {
+                const int q = __builtin_amdgcn_readfirstlane(qy * bins.QX + qx);
+                empty = (bins.fcnt[q] | bins.cnt[q] | bins.total[1]) == 0;
+            } else {
+                empty = true;  // every pixel of the quadrant is outside the image
+            }
+        }
+        if (empty) d = make_float3(0.f, 0.f, 1.f);  // no ray to set up: every lane misses
+        else d = camera_dir(cam, row, col);
         o = make_float3(cam.o[0], cam.o[1], cam.o[2]);
     } else {
         ray = int64_t(blockIdx.x) * kThreads + threadIdx.x;
@@ -443,9 +453,15 @@ __global__ __launch_bounds__(kThreads) void k_trace(ModelC m, CamSet<NCAM> cams,
     int32_t tri = -1;
     const bool active = valid && finite;
     if (CAMERA) {
-        const RayPre R = ray_setup(o, active ? d : make_float3(0.f, 0.f, 1.f));
-        if constexpr (BINNED) closest_hit_binned(m, bins, qx, qy, R, active, wst + wave * kBvhMaxStack, t, tri);
-        else closest_hit_packet(m, R, active, wst + wave * kBvhMaxStack, t, tri);
+        if constexpr (BINNED) {
+            if (!empty) {
+                const RayPre R = ray_setup(o, active ? d : make_float3(0.f, 0.f, 1.f));
+                closest_hit_binned(m, bins, qx, qy, R, active, wst + wave * kBvhMaxStack, t, tri);
+            }
+        } else {
+            const RayPre R = ray_setup(o, active ? d : make_float3(0.f, 0.f, 1.f));
+            closest_hit_packet(m, R, active, wst + wave * kBvhMaxStack, t, tri);
+        }
     } else if (active) {
         const RayPre R = ray_setup(o, d);
         closest_hit(m, R, stack + threadIdx.x, t, tri);
@@ -646,7 +662,7 @@ struct ShadeShape {
 // NOLF (the paper's own i-NOLF form): the record's pad holds the ray's
 // coarse opacity, a further network input, and the colour buffer holds the
 // diffuse colour and tint of the hit, which the outputs complete as
-// (c_d + t c_s, alpha).  With cam->W > 0 the records are the CamHit records
+// (c_d + t c_s, alpha).  With cam.W > 0 the records are the CamHit records
 // of that camera's frame.
 template <class TableT, class P, int LPG, bool NOLF, class M>
 __device__ __forceinline__ void shade_step(const M& m, const typename Mfma<P>::vec* W,
