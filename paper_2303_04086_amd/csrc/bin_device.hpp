@@ -284,8 +284,9 @@ __device__ __forceinline__ float wave_max_best(bool active, float best_t) {
 
 // Entries [s, e) of a quadrant's list against the wave's rays, with the axes
 // of the watertight test given by Ax, four at a time: the four records, then
-// their triangles, are requested before any test waits on them.  With SKIP,
-// entries whose distance bound exceeds tmax are not tested.
+// their triangles, are requested before any test waits on them (past e, the
+// first of the four is requested again but not tested).  With SKIP, entries
+// whose distance bound exceeds tmax are not tested.
 template <bool SKIP, class Ax>
 __device__ __forceinline__ void bin_walk(const RayPre& R, const Ax& ax, const int2* __restrict__ ent,
                                          const float4* __restrict__ tv, int s, int e, float tmax, bool active,
@@ -297,7 +298,7 @@ __device__ __forceinline__ void bin_walk(const RayPre& R, const Ax& ax, const in
         for (int u = 0; u < 4; ++u) {
             const int2 en = ent[k + u < e ? k + u : k];
             r[u] = __builtin_amdgcn_readfirstlane(en.x);
-            go[u] = !SKIP || !(__int_as_float(__builtin_amdgcn_readfirstlane(en.y)) > tmax);
+            go[u] = k + u < e && (!SKIP || !(__int_as_float(__builtin_amdgcn_readfirstlane(en.y)) > tmax));
         }
         if (SKIP && !(go[0] || go[1] || go[2] || go[3])) continue;
         float4 v[12];
