@@ -593,6 +593,28 @@ __global__ __launch_bounds__(kThreads) void k_compact(const int2* __restrict__ b
     }
 }
 
+// k_compact for a single object: one wave per workgroup run of the trace
+// (a camera tile or a block of rays), four runs per workgroup, so a frame's
+// many empty tiles cost one wave each rather than one workgroup.
+template <class Rec>
+__global__ __launch_bounds__(kThreads) void k_compact_runs(const int2* __restrict__ blk,
+                                                           const int32_t* __restrict__ offsets,
+                                                           const int32_t* __restrict__ runs, const Rec* __restrict__ tmp,
+                                                           Rec* __restrict__ recs, int n_blk) {
+    constexpr int kWords = int(sizeof(Rec) / sizeof(float4));
+    const int j = __builtin_amdgcn_readfirstlane(int(blockIdx.x) * (kThreads / 64) + int(threadIdx.x) / 64);
+    if (j >= n_blk) return;
+    const int2 b = blk[j];
+    if (b.x == 0) return;
+    const int dst = offsets[j] + runs[j / kScanRun];
+    for (int i = __lane_id(); i < b.x; i += 64) {
+        const float4* src = reinterpret_cast<const float4*>(tmp + b.y + i);
+        float4* out = reinterpret_cast<float4*>(recs + dst + i);
+#pragma unroll
+        for (int w = 0; w < kWords; ++w) out[w] = src[w];
+    }
+}
+
 // ------------------------------------------------------------- shading ----
 
 // Network kernels are declared to fit in at most 256 registers per lane (at
@@ -1472,12 +1494,13 @@ void trace_to_hits(const ModelC& c, const CamSet<NCAM>* cams, const float* ray_o
     hipLaunchKernelGGL(k_scan_runs, dim3(1), dim3(kScanThreads), 0, s, runs, n_runs, counter, counter + 1,
                        kMaxChunks - 1);
     launch_check("k_scan_runs");
+    const dim3 cgrid(unsigned((n_blk + kThreads / 64 - 1) / (kThreads / 64)));
     if (cams && NCAM == 1)
-        hipLaunchKernelGGL(k_compact<CamHit>, dim3(n_blk), dim3(kThreads), 0, s, blk, offsets, runs,
-                           static_cast<const CamHit*>(a.tmp), ws_at<CamHit>(ws, L.recs), 1, n_blk);
+        hipLaunchKernelGGL(k_compact_runs<CamHit>, cgrid, dim3(kThreads), 0, s, blk, offsets, runs,
+                           static_cast<const CamHit*>(a.tmp), ws_at<CamHit>(ws, L.recs), n_blk);
     else
-        hipLaunchKernelGGL(k_compact<HitRec>, dim3(n_blk), dim3(kThreads), 0, s, blk, offsets, runs,
-                           static_cast<const HitRec*>(a.tmp), recs, 1, n_blk);
+        hipLaunchKernelGGL(k_compact_runs<HitRec>, cgrid, dim3(kThreads), 0, s, blk, offsets, runs,
+                           static_cast<const HitRec*>(a.tmp), recs, n_blk);
     launch_check("k_compact");
 }
 
